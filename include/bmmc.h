@@ -1,0 +1,323 @@
+/*
+ * bmmc.h -- C interface of the MI355X BMMC permutation library (libbmmc.so).
+ *
+ * Operation (Bouverot-Dupuis & Sheeran, "Efficient GPU Implementation of
+ * Affine Index Permutations on Arrays", FHPNC '23; Section 3, the affine map
+ * y = A.x + c over F_2 and its per-bit expansion; Section 4.1, the kernel
+ * that writes the element read at input index x to output index p(x) XOR c):
+ *
+ *     out[A.x XOR c] = in[x]     for every x in [0, 2^n)
+ *
+ * where an index x is the bit vector (x_0 .. x_{n-1}), bit 0 least
+ * significant, A is an invertible n x n matrix over F_2 and c an n-bit
+ * vector.  Elements are opaque blocks of elem_bytes bytes.
+ *
+ * Conventions shared by every entry point
+ *   - A_rows: host array of n uint64 words; bit j of A_rows[i] is entry a_ij
+ *     (row i produces output bit i).  Bits at positions >= n must be zero,
+ *     as must bits of c at positions >= n.  The library copies A_rows and c
+ *     before returning; the caller may free them at once.
+ *   - in / out: device pointers owned by the caller, 16-byte aligned,
+ *     2^n * elem_bytes bytes each, not overlapping (the method is out of
+ *     place).  Ownership never passes to the library.
+ *   - elem_bytes: 1, 2, 4, 8 or 16.  n: 0 .. BMMC_MAX_BITS.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *     entry points only enqueue work and return; results are visible after
+ *     the stream is synchronized.  Faults inside kernels surface at that
+ *     synchronization, not as a return code.
+ *   - Return value: BMMC_OK (0) or a negative bmmc_status.  Arguments are
+ *     validated before anything is enqueued, so an error return means no work
+ *     was queued.  bmmc_last_error() gives a message for the calling thread.
+ *   - Thread safety: every entry point may be called from several host
+ *     threads; plans and scratch buffers are cached per device and stream.
+ */
+#ifndef BMMC_H
+#define BMMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMMC_MAX_BITS 32
+#define BMMC_VERSION 100
+
+typedef enum {
+    BMMC_OK = 0,
+    BMMC_ERR_ARG = -1,      /* null pointer, bad width, bits beyond n, misaligned */
+    BMMC_ERR_SINGULAR = -2, /* A is not invertible over F_2 */
+    BMMC_ERR_RANGE = -3,    /* n, t or a tile size out of the supported range */
+    BMMC_ERR_ALIAS = -4,    /* in and out overlap */
+    BMMC_ERR_NOMEM = -5,    /* device or host allocation failed / budget exceeded */
+    BMMC_ERR_HIP = -6,      /* a HIP runtime call failed (message in bmmc_last_error) */
+    BMMC_ERR_INTERNAL = -7, /* planner invariant violated (a bug) */
+    BMMC_ERR_NOTFOUND = -8, /* unknown ticket or handle */
+    BMMC_ERR_BUSY = -9      /* request not finished yet (non-blocking poll) */
+} bmmc_status;
+
+/* How a permutation is carried out. */
+typedef enum {
+    /* The paper's scheme (Sections 5.1-5.2): one LDS-staged pass when A is
+       tiled or the whole array fits one tile, otherwise the factorization
+       A = (U.R)(R.L.P) and two passes through a library-owned scratch array. */
+    BMMC_METHOD_AUTO = 0,
+    BMMC_METHOD_TILED = 1,   /* same as AUTO */
+    /* One pass for any A: the tile is the span of the low t input bits and of
+       the inputs that reach the low t output bits (not in the paper). */
+    BMMC_METHOD_ONEPASS = 2,
+    /* Lower bound: one lane per element, coalesced reads, scattered writes
+       (the paper's naive kernels, Appendix). */
+    BMMC_METHOD_NAIVE = 3
+} bmmc_method;
+
+/* Tuning knobs of one call; zero means "library default". */
+typedef struct {
+    int method;    /* bmmc_method */
+    int t;         /* run bits: reads and writes move runs of 2^t elements */
+    int threads;   /* work-group size: 256, 512 or 1024 */
+    int iters;     /* 16-byte vectors per thread per tile */
+    int swizzle;   /* 1 (default) conflict-avoiding LDS layout, -1 plain layout */
+    int grid;      /* work-groups per pass launch; 0 = one per tile */
+    int reserved[2];
+} bmmc_options_t;
+
+/* Result of planning one permutation (plain data, caller-owned, no free).
+   Factor k is (rows[k], c[k]); factor 0 is applied first.  With two factors
+   c[0] = 0 and c[1] = c (Section 5.2). */
+typedef struct {
+    int n, t, nfactors;        /* nfactors: 1 or 2 (0 when n == 0) */
+    int elem_bytes;
+    uint64_t rows[2][64];
+    uint64_t c[2];
+    uint64_t col_mask[2];      /* tile column bits: the low t input bits */
+    uint64_t tile_rows_mask[2];/* tile row bits: inputs whose images are the low t outputs */
+    uint64_t iter_mask[2];     /* iteration bits folded into the tile (Section 4.3) */
+    uint64_t tb_mask[2];       /* bits that select the tile (one tile per value) */
+    int n_over[2];             /* |col bits AND row bits| */
+    int tile_bits[2];          /* log2 of elements per tile */
+    int coordinate[2];         /* 1 when the tile is spanned by index bits */
+    int lds_conflict_score[2]; /* 0 = every wave LDS access conflict-free */
+} bmmc_plan_t;
+
+/* One array of a batched call. */
+typedef struct {
+    const void* in;
+    void* out;
+    int n;
+    int elem_bytes;
+    const uint64_t* A_rows;
+    uint64_t c;
+} bmmc_desc_t;
+
+/* Knobs of the batched persistent kernel; zero means default / autotuned. */
+typedef struct {
+    int workgroups;     /* persistent work-groups (default: fill every CU) */
+    int chunk_tiles;    /* tiles per work item */
+    int order;          /* 0 = largest arrays first, 1 = input order, 2 = interleaved */
+    int use_graph;      /* 1 (default): replay a captured hipGraph; -1: plain launch */
+    int method;         /* bmmc_method for the arrays that need two passes */
+    int reserved[3];
+} bmmc_batch_options_t;
+
+/* Per-kernel timing gathered between bmmc_profile_begin and _end. */
+typedef struct {
+    char name[48];
+    int launches;
+    double total_ms;
+    double bytes;       /* algorithmic bytes moved by those launches (read + write) */
+} bmmc_kernel_stat_t;
+
+/* Host emulation counters (see bmmc_emulate). */
+typedef struct {
+    int64_t tiles;
+    int64_t read_instr, write_instr;      /* wave-level global accesses */
+    int64_t read_lines, write_lines;      /* distinct 128-byte lines they touch */
+    int64_t read_lines_min, write_lines_min;
+    int64_t lds_instr;                    /* wave-level LDS accesses */
+    int64_t lds_conflicts32, lds_conflicts64; /* extra cycles beyond 1 per group */
+    int64_t lds_slot_errors;              /* slots not written exactly once / read exactly once */
+} bmmc_emu_stats_t;
+
+/* ------------------------------------------------------------ utilities */
+
+/* Message for a status code.  Static string; never NULL. */
+const char* bmmc_strerror(int status);
+/* Message of the last failed call on this host thread ("" if none). */
+const char* bmmc_last_error(void);
+int bmmc_version(void);
+
+/* --------------------------------------------------- host-only planning */
+
+/* Tiled test (Section 5.1): is there a set S of t columns whose first t
+   rows form an invertible block and whose last n-t rows are zero?  Returns
+   1 (tiled; *rows_mask_out = S when not NULL), 0 (not tiled) or a negative
+   status.  Host only; touches no device. */
+int bmmc_is_tiled(const uint64_t* A_rows, int n, int t, uint64_t* rows_mask_out);
+
+/* Factorization (Section 5.2): fills *plan_out with one factor (A, c) when A
+   is tiled at the default t or 2^n fits one tile, else with
+   (R.L.P, 0) then (U.R, c) where A = U.L.P.  bmmc_factorize_t picks t.
+   Host only.  Errors: BMMC_ERR_ARG, _SINGULAR, _RANGE. */
+int bmmc_factorize(const uint64_t* A_rows, uint64_t c, int n, bmmc_plan_t* plan_out);
+int bmmc_factorize_t(const uint64_t* A_rows, uint64_t c, int n, int t, int elem_bytes,
+                     bmmc_plan_t* plan_out);
+
+/* The plan bmmc_permute_ex would run with these options (tile shape from
+   threads / iters / t; NULL = defaults), for inspection.  The kernel for
+   that shape need not exist.  Host only.  Errors: _ARG, _SINGULAR, _RANGE. */
+int bmmc_plan_ex(const uint64_t* A_rows, uint64_t c, int n, int elem_bytes,
+                 const bmmc_options_t* opts, bmmc_plan_t* plan_out);
+
+/* The raw factorization of Section 5.2: A = U.L.P with U upper
+   unitriangular, L lower unitriangular and P a permutation matrix, and the
+   tiled factors T1 = U.R, T2 = R.L.P (R the bit reversal), so A = T1.T2.
+   Each output is a host array of n rows in the A_rows encoding; any may be
+   NULL.  Host only.  Errors: _ARG, _RANGE, _SINGULAR. */
+int bmmc_factorize_ulp(const uint64_t* A_rows, int n, uint64_t* U, uint64_t* L, uint64_t* P,
+                       uint64_t* T1, uint64_t* T2);
+
+/* Host emulation of the tiled kernels' address arithmetic, for tests: runs
+   the same plan, tile by tile and lane by lane, on host memory (in/out are
+   HOST pointers here) and counts coalescing, LDS bank conflicts and LDS
+   slot use.  Never used by the device entry points.  stats may be NULL. */
+int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                 int elem_bytes, const bmmc_options_t* opts, bmmc_emu_stats_t* stats);
+
+/* ------------------------------------------------------- device calls */
+
+/* The permutation out[A.x XOR c] = in[x] by the paper's scheme (one or two
+   LDS-staged tiled passes).  Plans are cached by (A, c, n, elem_bytes);
+   two-pass plans use a scratch array of 2^n * elem_bytes owned by the
+   library (kept per device and stream, grown on demand).
+   Errors: _ARG, _SINGULAR, _RANGE, _ALIAS, _NOMEM, _HIP. */
+int bmmc_permute(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                 int elem_bytes, void* stream);
+
+/* Same operation with explicit options (method, tile width, launch shape). */
+int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                    int elem_bytes, const bmmc_options_t* opts, void* stream);
+
+/* Lower bound of the paper's ablation (Appendix naive kernel): one lane per
+   element, coalesced read, write scattered to A.x XOR c. */
+int bmmc_permute_naive(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                       int elem_bytes, void* stream);
+
+/* Upper bound (Section 2.3 "copy"): out[i] = in[i] for `bytes` bytes with
+   16-byte vector loads and stores.  Pointers must not overlap. */
+int bmmc_copy(const void* in, void* out, size_t bytes, void* stream);
+
+/* Many independent permutations, each with its own n, width, A and c, in one
+   persistent kernel launch replayed from a captured hipGraph.  Arrays that fit
+   one tile take one pass; the others take the paper's two tiled passes, the
+   second pass of an array starting once its first pass is complete.  descs is
+   a host array of `count` descriptors; every in/out pair obeys the rules
+   above and no out may overlap another array's in or out.  Scratch, the
+   device descriptor table and the graph are owned by the library.
+   Errors: as bmmc_permute, reported for the first bad descriptor. */
+int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream);
+int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count,
+                            const bmmc_batch_options_t* opts, void* stream);
+
+/* Wait for `stream` and report in *timed_out whether the last batched launch
+   on it gave up waiting for a first pass (1) or not (0).  The persistent
+   kernel bounds every wait instead of hanging; a timeout means its output is
+   incomplete.  Errors: _HIP. */
+int bmmc_batched_status(void* stream, int* timed_out);
+
+/* ------------------------------------------------------------- autotuner */
+
+/* Time the available tile shapes (threads x iterations), run widths t and
+   grid sizes on a random permutation of 2^n elements of elem_bytes bytes with
+   `method`, `reps` timed runs each, on `stream` (synchronizes it).  The
+   fastest is cached for (n, elem_bytes, method) and used by later calls that
+   pass no options; it is also returned.  Allocates two temporary buffers of
+   2^n * elem_bytes.  Errors: _RANGE, _ARG, _NOMEM, _HIP. */
+int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
+                  bmmc_options_t* best_out, double* best_ms);
+
+/* Time chunk size, queue order and persistent grid size of the batched
+   kernel on this very batch (it runs the batch 1 + reps times per candidate);
+   the fastest is cached for batches with the same histogram of (n, width). */
+int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* stream, int reps,
+                          bmmc_batch_options_t* best_out, double* best_ms);
+
+/* Save / load the tuning cache as JSON lines.  BMMC_TUNE_CACHE, when set,
+   names a file loaded on first use and rewritten after each tuning run.
+   bmmc_tune_load returns the number of entries read. */
+int bmmc_tune_save(const char* path);
+int bmmc_tune_load(const char* path);
+
+/* --------------------------------------------------------------- serving */
+
+typedef struct {
+    int64_t budget_bytes; /* HBM budget: input + output + scratch of admitted requests */
+    int streams;          /* concurrent batched launches (default 4, at most 16) */
+    int max_batch;        /* requests per launch (0 = all admitted) */
+    /* 0: the caller passes `out`; 1: the server allocates `out` from its
+       arena and keeps it until bmmc_server_release; 2: as 1, but the output
+       is dropped at completion and the ticket forgotten (load generation). */
+    int own_outputs;
+    int method;           /* bmmc_method for two-pass-sized arrays */
+    int reserved[4];
+} bmmc_server_options_t;
+
+typedef struct {
+    int64_t submitted, completed, rejected, batches;
+    double bytes_moved;   /* algorithmic bytes (read + write) of completed requests */
+    double busy_s;        /* first arrival to last completion */
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival-to-completion latency */
+    int64_t in_use_bytes, peak_bytes;
+    double mean_batch;    /* requests per launch */
+    double reserved[4];
+} bmmc_server_stats_t;
+
+/* A continuous-batching server on the current device.  It allocates one
+   device arena (the largest power of two <= budget_bytes) for outputs and
+   scratch, `streams` HIP streams at default priority, and two host threads.
+   Requests are admitted in arrival order while input + output + scratch of
+   all admitted, unfinished requests fits budget_bytes; every admitted request
+   joins the next batched launch on a free stream.
+   Errors: _ARG, _NOMEM. */
+int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out);
+
+/* Queue one permutation.  desc->in must stay valid and unchanged until the
+   request completes; desc->out is used only when own_outputs == 0.  A_rows is
+   copied.  arrival_ns is on the bmmc_server_now_ns clock (0 = now); a future
+   time holds the request back until then, and latency is measured from it.
+   Errors: _ARG, _RANGE, _NOMEM (can never fit the budget). */
+int bmmc_server_submit(void* handle, const bmmc_desc_t* desc, int64_t arrival_ns, int64_t* ticket_out);
+
+/* State of a ticket: BMMC_OK with the completion time and output pointer,
+   BMMC_ERR_BUSY while pending (wait = 0), or the error the request failed
+   with.  wait != 0 blocks until completion. */
+int bmmc_server_poll(void* handle, int64_t ticket, int wait, int64_t* done_ns, void** out_ptr);
+
+/* Forget a finished ticket and free its output (own_outputs == 1). */
+int bmmc_server_release(void* handle, int64_t ticket);
+
+/* Block until every submitted request has finished. */
+int bmmc_server_drain(void* handle);
+
+int bmmc_server_stats(void* handle, bmmc_server_stats_t* stats);
+
+/* Stop the server threads, wait for its streams and free its memory. */
+int bmmc_server_destroy(void* handle);
+
+/* The server's clock (steady clock, nanoseconds). */
+int64_t bmmc_server_now_ns(void);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Start recording a hipEvent pair around every kernel launch the library
+   makes on this device; bmmc_profile_end waits for them, fills up to `max`
+   entries (one per kernel name) and returns how many it filled. */
+int bmmc_profile_begin(void);
+int bmmc_profile_end(bmmc_kernel_stat_t* out, int max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMMC_H */

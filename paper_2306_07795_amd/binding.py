@@ -1,0 +1,403 @@
+"""ctypes binding of libbmmc.so: the C entry points under the same names.
+
+Argument marshalling only: every step of a permutation runs in the library's
+HIP kernels.  Device buffers are passed as integers (device addresses) or as
+objects with ``data_ptr()`` (e.g. torch tensors); streams as integers or as
+objects with a ``cuda_stream`` attribute (torch streams).  A non-zero status
+raises ``BmmcError`` carrying the library's message.  If the library has not
+been built this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmmc.so")
+
+MAX_BITS = 32
+METHOD_AUTO, METHOD_TILED, METHOD_ONEPASS, METHOD_NAIVE = 0, 1, 2, 3
+
+_c = ctypes
+_u64, _i32, _i64, _vp, _dbl = _c.c_uint64, _c.c_int, _c.c_int64, _c.c_void_p, _c.c_double
+
+
+class BmmcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"bmmc status {status}: {message}")
+        self.status = status
+
+
+class Options(_c.Structure):
+    _fields_ = [("method", _i32), ("t", _i32), ("threads", _i32), ("iters", _i32),
+                ("swizzle", _i32), ("grid", _i32), ("reserved", _i32 * 2)]
+
+
+class Plan(_c.Structure):
+    _fields_ = [("n", _i32), ("t", _i32), ("nfactors", _i32), ("elem_bytes", _i32),
+                ("rows", (_u64 * 64) * 2), ("c", _u64 * 2), ("col_mask", _u64 * 2),
+                ("tile_rows_mask", _u64 * 2), ("iter_mask", _u64 * 2), ("tb_mask", _u64 * 2),
+                ("n_over", _i32 * 2), ("tile_bits", _i32 * 2), ("coordinate", _i32 * 2),
+                ("lds_conflict_score", _i32 * 2)]
+
+    def factor(self, k: int):
+        """(rows, c) of factor k as Python ints."""
+        return [int(self.rows[k][i]) for i in range(self.n)], int(self.c[k])
+
+
+class Desc(_c.Structure):
+    _fields_ = [("in_", _vp), ("out", _vp), ("n", _i32), ("elem_bytes", _i32),
+                ("A_rows", _c.POINTER(_u64)), ("c", _u64)]
+
+
+class BatchOptions(_c.Structure):
+    _fields_ = [("workgroups", _i32), ("chunk_tiles", _i32), ("order", _i32),
+                ("use_graph", _i32), ("method", _i32), ("reserved", _i32 * 3)]
+
+
+class KernelStat(_c.Structure):
+    _fields_ = [("name", _c.c_char * 48), ("launches", _i32), ("total_ms", _dbl), ("bytes", _dbl)]
+
+
+class EmuStats(_c.Structure):
+    _fields_ = [(f, _i64) for f in (
+        "tiles", "read_instr", "write_instr", "read_lines", "write_lines", "read_lines_min",
+        "write_lines_min", "lds_instr", "lds_conflicts32", "lds_conflicts64", "lds_slot_errors")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class ServerStats(_c.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("batches", _i64),
+                ("bytes_moved", _dbl), ("busy_s", _dbl), ("p50_ms", _dbl), ("p99_ms", _dbl),
+                ("mean_ms", _dbl), ("max_ms", _dbl), ("in_use_bytes", _i64), ("peak_bytes", _i64),
+                ("mean_batch", _dbl), ("reserved", _dbl * 4)]
+
+
+class ServerOptions(_c.Structure):
+    _fields_ = [("budget_bytes", _i64), ("streams", _i32), ("max_batch", _i32),
+                ("own_outputs", _i32), ("method", _i32), ("reserved", _i32 * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbmmc.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_07795_amd.build`")
+    L = _c.CDLL(LIB_PATH)
+    P = _c.POINTER
+    sig = {
+        "bmmc_strerror": (_c.c_char_p, [_i32]),
+        "bmmc_last_error": (_c.c_char_p, []),
+        "bmmc_version": (_i32, []),
+        "bmmc_is_tiled": (_i32, [P(_u64), _i32, _i32, P(_u64)]),
+        "bmmc_factorize": (_i32, [P(_u64), _u64, _i32, P(Plan)]),
+        "bmmc_factorize_t": (_i32, [P(_u64), _u64, _i32, _i32, _i32, P(Plan)]),
+        "bmmc_emulate": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, P(Options), P(EmuStats)]),
+        "bmmc_plan_ex": (_i32, [P(_u64), _u64, _i32, _i32, P(Options), P(Plan)]),
+        "bmmc_factorize_ulp": (_i32, [P(_u64), _i32, P(_u64), P(_u64), P(_u64), P(_u64), P(_u64)]),
+        "bmmc_permute": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
+        "bmmc_permute_ex": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, P(Options), _vp]),
+        "bmmc_permute_naive": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
+        "bmmc_copy": (_i32, [_vp, _vp, _c.c_size_t, _vp]),
+        "bmmc_permute_batched": (_i32, [P(Desc), _i32, _vp]),
+        "bmmc_permute_batched_ex": (_i32, [P(Desc), _i32, P(BatchOptions), _vp]),
+        "bmmc_batched_status": (_i32, [_vp, P(_i32)]),
+        "bmmc_profile_begin": (_i32, []),
+        "bmmc_profile_end": (_i32, [P(KernelStat), _i32]),
+        "bmmc_autotune_batched": (_i32, [P(Desc), _i32, _vp, _i32, P(BatchOptions), P(_dbl)]),
+        "bmmc_autotune": (_i32, [_i32, _i32, _i32, _vp, _i32, P(Options), P(_dbl)]),
+        "bmmc_tune_save": (_i32, [_c.c_char_p]),
+        "bmmc_tune_load": (_i32, [_c.c_char_p]),
+        "bmmc_server_create": (_i32, [P(ServerOptions), P(_vp)]),
+        "bmmc_server_destroy": (_i32, [_vp]),
+        "bmmc_server_submit": (_i32, [_vp, P(Desc), _i64, P(_i64)]),
+        "bmmc_server_poll": (_i32, [_vp, _i64, _i32, P(_i64), P(_vp)]),
+        "bmmc_server_release": (_i32, [_vp, _i64]),
+        "bmmc_server_drain": (_i32, [_vp]),
+        "bmmc_server_stats": (_i32, [_vp, P(ServerStats)]),
+        "bmmc_server_now_ns": (_i64, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_names():
+    return [
+        "bmmc_strerror", "bmmc_last_error", "bmmc_version", "bmmc_is_tiled", "bmmc_factorize",
+        "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
+        "bmmc_copy", "bmmc_permute_batched", "bmmc_permute_batched_ex", "bmmc_batched_status",
+        "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
+        "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
+        "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
+        "bmmc_server_stats", "bmmc_server_now_ns",
+    ]
+
+
+# ------------------------------------------------------------- marshalling
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if hasattr(x, "ctypes"):
+        return int(x.ctypes.data)
+    raise TypeError(f"cannot take a device address from {type(x)!r}")
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s or None
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream) or None
+    raise TypeError(f"cannot take a stream from {type(s)!r}")
+
+
+def _rows(A_rows, n):
+    arr = (_u64 * max(n, 1))()
+    for i in range(n):
+        arr[i] = int(A_rows[i])
+    return arr
+
+
+def _check(status: int):
+    if status < 0:
+        raise BmmcError(status, lib().bmmc_last_error().decode(errors="replace"))
+    return status
+
+
+def _options(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, Options):
+        return _c.byref(opts)
+    o = Options()
+    for k, v in dict(opts).items():
+        setattr(o, k, int(v))
+    return _c.byref(o)
+
+
+# ------------------------------------------------------------ entry points
+
+def bmmc_strerror(status: int) -> str:
+    return lib().bmmc_strerror(status).decode()
+
+
+def bmmc_version() -> int:
+    return lib().bmmc_version()
+
+
+def bmmc_is_tiled(A_rows, n: int, t: int):
+    """(tiled?, tile row mask)."""
+    mask = _u64(0)
+    r = _check(lib().bmmc_is_tiled(_rows(A_rows, n), n, t, _c.byref(mask)))
+    return bool(r), int(mask.value)
+
+
+def bmmc_factorize(A_rows, c: int, n: int) -> Plan:
+    p = Plan()
+    _check(lib().bmmc_factorize(_rows(A_rows, n), c, n, _c.byref(p)))
+    return p
+
+
+def bmmc_factorize_t(A_rows, c: int, n: int, t: int, elem_bytes: int = 4) -> Plan:
+    p = Plan()
+    _check(lib().bmmc_factorize_t(_rows(A_rows, n), c, n, t, elem_bytes, _c.byref(p)))
+    return p
+
+
+def bmmc_plan_ex(A_rows, c: int, n: int, elem_bytes: int = 4, opts=None) -> Plan:
+    p = Plan()
+    _check(lib().bmmc_plan_ex(_rows(A_rows, n), c, n, elem_bytes, _options(opts), _c.byref(p)))
+    return p
+
+
+def bmmc_factorize_ulp(A_rows, n: int):
+    """dict of U, L, P, T1, T2 (lists of n row words) with A = U.L.P = T1.T2."""
+    outs = {k: (_u64 * max(n, 1))() for k in ("U", "L", "P", "T1", "T2")}
+    _check(lib().bmmc_factorize_ulp(_rows(A_rows, n), n, outs["U"], outs["L"], outs["P"],
+                                    outs["T1"], outs["T2"]))
+    return {k: [int(v[i]) for i in range(n)] for k, v in outs.items()}
+
+
+def bmmc_emulate(inp, out, n: int, A_rows, c: int, elem_bytes: int, opts=None) -> dict:
+    """Host emulation of the kernels; inp/out are host buffers (numpy arrays)."""
+    st = EmuStats()
+    _check(lib().bmmc_emulate(_ptr(inp), _ptr(out), n, _rows(A_rows, n), c, elem_bytes,
+                              _options(opts), _c.byref(st)))
+    return st.as_dict()
+
+
+def bmmc_permute(inp, out, n: int, A_rows, c: int, elem_bytes: int, stream=None):
+    _check(lib().bmmc_permute(_ptr(inp), _ptr(out), n, _rows(A_rows, n), c, elem_bytes,
+                              _stream(stream)))
+
+
+def bmmc_permute_ex(inp, out, n: int, A_rows, c: int, elem_bytes: int, opts=None, stream=None):
+    _check(lib().bmmc_permute_ex(_ptr(inp), _ptr(out), n, _rows(A_rows, n), c, elem_bytes,
+                                 _options(opts), _stream(stream)))
+
+
+def bmmc_permute_naive(inp, out, n: int, A_rows, c: int, elem_bytes: int, stream=None):
+    _check(lib().bmmc_permute_naive(_ptr(inp), _ptr(out), n, _rows(A_rows, n), c, elem_bytes,
+                                    _stream(stream)))
+
+
+def bmmc_copy(inp, out, nbytes: int, stream=None):
+    _check(lib().bmmc_copy(_ptr(inp), _ptr(out), nbytes, _stream(stream)))
+
+
+def make_descs(items):
+    """items: iterable of (in, out, n, elem_bytes, A_rows, c).  Returns a
+    ctypes array of Desc plus the row arrays it points into (keep both alive)."""
+    items = list(items)
+    arr = (Desc * max(len(items), 1))()
+    keep = []
+    for k, (i, o, n, w, rows, c) in enumerate(items):
+        r = _rows(rows, n)
+        keep.append(r)
+        arr[k].in_ = _ptr(i)
+        arr[k].out = _ptr(o)
+        arr[k].n = n
+        arr[k].elem_bytes = w
+        arr[k].A_rows = _c.cast(r, _c.POINTER(_u64))
+        arr[k].c = c
+    return arr, keep, len(items)
+
+
+def _batch_options(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, BatchOptions):
+        return _c.byref(opts)
+    o = BatchOptions()
+    for k, v in dict(opts).items():
+        setattr(o, k, int(v))
+    return _c.byref(o)
+
+
+def bmmc_permute_batched(items, stream=None, opts=None):
+    arr, keep, count = make_descs(items)
+    if opts is None:
+        _check(lib().bmmc_permute_batched(arr, count, _stream(stream)))
+    else:
+        _check(lib().bmmc_permute_batched_ex(arr, count, _batch_options(opts), _stream(stream)))
+    del keep
+
+
+def bmmc_batched_status(stream=None) -> bool:
+    """Synchronizes the stream; True if the last batched launch gave up a wait."""
+    flag = _i32(0)
+    _check(lib().bmmc_batched_status(_stream(stream), _c.byref(flag)))
+    return bool(flag.value)
+
+
+def bmmc_profile_begin():
+    _check(lib().bmmc_profile_begin())
+
+
+def bmmc_profile_end(max_kernels: int = 64):
+    arr = (KernelStat * max_kernels)()
+    k = _check(lib().bmmc_profile_end(arr, max_kernels))
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                   "bytes": arr[i].bytes} for i in range(k)}
+
+
+def bmmc_autotune(n: int, elem_bytes: int, method: int = METHOD_AUTO, stream=None, reps: int = 5):
+    """Time the tile shapes for random permutations of this size; the best is
+    cached and used by later calls.  Returns (options dict, best ms)."""
+    o = Options()
+    ms = _dbl(0)
+    _check(lib().bmmc_autotune(n, elem_bytes, method, _stream(stream), reps, _c.byref(o),
+                               _c.byref(ms)))
+    return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}, ms.value
+
+
+def bmmc_autotune_batched(items, stream=None, reps: int = 3):
+    arr, keep, count = make_descs(items)
+    o = BatchOptions()
+    ms = _dbl(0)
+    _check(lib().bmmc_autotune_batched(arr, count, _stream(stream), reps, _c.byref(o), _c.byref(ms)))
+    del keep
+    return {f: getattr(o, f) for f, _ in BatchOptions._fields_ if f != "reserved"}, ms.value
+
+
+def bmmc_tune_save(path: str):
+    _check(lib().bmmc_tune_save(path.encode()))
+
+
+def bmmc_tune_load(path: str):
+    return _check(lib().bmmc_tune_load(path.encode()))
+
+
+# ---------------------------------------------------------------- serving
+
+def bmmc_server_create(budget_bytes: int, streams: int = 4, max_batch: int = 0,
+                       own_outputs: bool = True, method: int = METHOD_AUTO):
+    o = ServerOptions()
+    o.budget_bytes = budget_bytes
+    o.streams = streams
+    o.max_batch = max_batch
+    o.own_outputs = 1 if own_outputs else 0
+    o.method = method
+    h = _vp()
+    _check(lib().bmmc_server_create(_c.byref(o), _c.byref(h)))
+    return h.value
+
+
+def bmmc_server_destroy(handle):
+    _check(lib().bmmc_server_destroy(handle))
+
+
+def bmmc_server_submit(handle, inp, out, n: int, A_rows, c: int, elem_bytes: int,
+                       arrival_ns: int = 0) -> int:
+    arr, keep, _ = make_descs([(inp, out, n, elem_bytes, A_rows, c)])
+    ticket = _i64(0)
+    _check(lib().bmmc_server_submit(handle, arr, arrival_ns, _c.byref(ticket)))
+    del keep
+    return int(ticket.value)
+
+
+def bmmc_server_poll(handle, ticket: int, wait: bool = False):
+    """None while pending; else (completion time ns, output device address)."""
+    done = _i64(0)
+    out = _vp()
+    st = lib().bmmc_server_poll(handle, ticket, 1 if wait else 0, _c.byref(done), _c.byref(out))
+    if st == -9:  # BMMC_ERR_BUSY
+        return None
+    _check(st)
+    return int(done.value), int(out.value or 0)
+
+
+def bmmc_server_release(handle, ticket: int):
+    _check(lib().bmmc_server_release(handle, ticket))
+
+
+def bmmc_server_drain(handle):
+    _check(lib().bmmc_server_drain(handle))
+
+
+def bmmc_server_stats(handle) -> dict:
+    s = ServerStats()
+    _check(lib().bmmc_server_stats(handle, _c.byref(s)))
+    return {f: (getattr(s, f) if f != "reserved" else None) for f, _ in ServerStats._fields_
+            if f != "reserved"}
+
+
+def bmmc_server_now_ns() -> int:
+    return int(lib().bmmc_server_now_ns())

@@ -1,0 +1,437 @@
+// Batched form: many arrays, each with its own n, width, A and c, in one
+// launch of the persistent kernel, replayed from a captured hipGraph.
+//
+// The host plans every array (plan cache), lays the passes and the work items
+// out in a pinned staging buffer, copies them to a device-resident table and
+// launches the graph [clear counters] -> [persistent kernel].  The graph's
+// kernel arguments are fixed device pointers (the item count lives in the
+// table), so one instantiated graph serves every call on a stream until the
+// table has to grow.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace bmmc {
+
+namespace {
+
+struct BatchState {
+    hipStream_t stream = nullptr;
+    // device table: [header (nitems, pad) | passes | items | counters+head+status]
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    void* host = nullptr;  // pinned staging of the same layout
+    size_t cap_passes = 0, cap_items = 0, cap_counters = 0;
+    hipEvent_t staged = nullptr;  // last copy out of the staging buffer
+    hipGraphExec_t exec = nullptr;
+    uint32_t exec_grid = 0;
+    uint32_t exec_spin = 0;
+};
+
+struct BatchRegistry {
+    std::mutex mu;
+    std::vector<BatchState*> states;  // one per (device, stream)
+    std::vector<int> devices;
+};
+
+BatchRegistry& registry() {
+    static BatchRegistry r;
+    return r;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t passes_off, items_off, counters_off, total;
+};
+
+Layout layout_for(size_t np, size_t ni, size_t nc) {
+    Layout L;
+    L.passes_off = 256;
+    L.items_off = align_up(L.passes_off + np * sizeof(BatchPass), 256);
+    L.counters_off = align_up(L.items_off + ni * sizeof(BatchItem), 256);
+    L.total = align_up(L.counters_off + (nc + 2) * sizeof(uint32_t), 256);
+    return L;
+}
+
+int ensure_capacity(BatchState* bs, size_t np, size_t ni, size_t nc) {
+    if (np <= bs->cap_passes && ni <= bs->cap_items && nc <= bs->cap_counters) return BMMC_OK;
+    np = std::max(np * 2, bs->cap_passes);
+    ni = std::max(ni * 2, bs->cap_items);
+    nc = std::max(nc * 2, bs->cap_counters);
+    Layout L = layout_for(np, ni, nc);
+    hipError_t e;
+    if (bs->dev) {
+        e = hipStreamSynchronize(bs->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        hipFree(bs->dev);
+        hipHostFree(bs->host);
+        bs->dev = bs->host = nullptr;
+    }
+    if (bs->exec) {
+        hipGraphExecDestroy(bs->exec);
+        bs->exec = nullptr;
+    }
+    e = hipMalloc(&bs->dev, L.total);
+    if (e != hipSuccess) {
+        bs->dev = nullptr;
+        return set_error(BMMC_ERR_NOMEM, "batch table of %zu bytes: %s", L.total, hipGetErrorString(e));
+    }
+    e = hipHostMalloc(&bs->host, L.total, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipFree(bs->dev);
+        bs->dev = nullptr;
+        bs->host = nullptr;
+        return set_error(BMMC_ERR_NOMEM, "pinned staging of %zu bytes: %s", L.total, hipGetErrorString(e));
+    }
+    bs->dev_bytes = L.total;
+    bs->cap_passes = np;
+    bs->cap_items = ni;
+    bs->cap_counters = nc;
+    return BMMC_OK;
+}
+
+BatchState* batch_state(hipStream_t stream, int device) {
+    auto& r = registry();
+    std::lock_guard<std::mutex> lk(r.mu);
+    for (size_t i = 0; i < r.states.size(); i++)
+        if (r.states[i]->stream == stream && r.devices[i] == device) return r.states[i];
+    auto* bs = new BatchState();
+    bs->stream = stream;
+    r.states.push_back(bs);
+    r.devices.push_back(device);
+    return bs;
+}
+
+// Capture [zero counters] -> [persistent kernel] into a graph for this state.
+int build_graph(BatchState* bs, uint32_t grid, uint32_t spin) {
+    if (bs->exec && bs->exec_grid == grid && bs->exec_spin == spin) return BMMC_OK;
+    if (bs->exec) {
+        hipGraphExecDestroy(bs->exec);
+        bs->exec = nullptr;
+    }
+    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
+    uint8_t* d = (uint8_t*)bs->dev;
+    hipStream_t cap;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cap);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    uint32_t* counters = (uint32_t*)(d + L.counters_off);
+    launch_zero(counters, (uint32_t)bs->cap_counters + 2, cap);
+    launch_batched((const BatchPass*)(d + L.passes_off), (const BatchItem*)(d + L.items_off),
+                   (const uint32_t*)d, counters, counters + bs->cap_counters,
+                   counters + bs->cap_counters + 1, grid, spin, cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&bs->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        bs->exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    bs->exec_grid = grid;
+    bs->exec_spin = spin;
+    return BMMC_OK;
+}
+
+}  // namespace
+
+int batch_validate(const bmmc_desc_t* descs, int count) {
+    if (count < 0 || (count > 0 && !descs)) return set_error(BMMC_ERR_ARG, "descs is NULL or count < 0");
+    struct Iv {
+        uintptr_t a, b;
+        int idx;
+        bool is_out;
+    };
+    std::vector<Iv> iv;
+    iv.reserve(2 * (size_t)count);
+    for (int i = 0; i < count; i++) {
+        const bmmc_desc_t& d = descs[i];
+        if (d.n < 0 || d.n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "array %d: n = %d out of range", i, d.n);
+        const int w = d.elem_bytes;
+        if (!(w == 1 || w == 2 || w == 4 || w == 8 || w == 16))
+            return set_error(BMMC_ERR_ARG, "array %d: elem_bytes = %d", i, w);
+        const size_t bytes = ((size_t)1 << d.n) * (size_t)w;
+        int st = validate_buffers(d.in, d.out, bytes);
+        if (st != BMMC_OK) return set_error(st, "array %d: %s", i, bmmc_last_error());
+        iv.push_back({(uintptr_t)d.in, (uintptr_t)d.in + bytes, i, false});
+        iv.push_back({(uintptr_t)d.out, (uintptr_t)d.out + bytes, i, true});
+    }
+    // No output may overlap any other interval (inputs may be shared).  In
+    // start order, an interval overlaps an earlier one exactly when it starts
+    // before the largest end seen so far.
+    std::sort(iv.begin(), iv.end(), [](const Iv& x, const Iv& y) { return x.a < y.a; });
+    uintptr_t end_any = 0, end_out = 0;
+    int idx_any = -1, idx_out = -1;
+    for (const Iv& v : iv) {
+        if (v.is_out && idx_any >= 0 && v.a < end_any)
+            return set_error(BMMC_ERR_ALIAS, "arrays %d and %d overlap", idx_any, v.idx);
+        if (!v.is_out && idx_out >= 0 && v.a < end_out)
+            return set_error(BMMC_ERR_ALIAS, "arrays %d and %d overlap", idx_out, v.idx);
+        if (v.b > end_any) {
+            end_any = v.b;
+            idx_any = v.idx;
+        }
+        if (v.is_out && v.b > end_out) {
+            end_out = v.b;
+            idx_out = v.idx;
+        }
+    }
+    return BMMC_OK;
+}
+
+
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out) {
+    PlanOptions po;
+    po.method = (method == BMMC_METHOD_ONEPASS) ? kMethodOnePass : kMethodAuto;
+    po.shape = default_shape(d.elem_bytes);
+    if (d.elem_bytes >= 4) {
+        po.shape.nt = batched_threads();
+        po.shape.iters = batched_iters();
+    }
+    int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, po, &out->plan);
+    if (st != BMMC_OK) return st;
+    out->in = d.in;
+    out->out = d.out;
+    out->scratch = nullptr;
+    out->bytes = ((size_t)1 << d.n) * (size_t)d.elem_bytes;
+    // Arrays of one element, too small for 16-byte vectors, or of 1- or
+    // 2-byte elements take the single-array kernels.
+    out->single = out->plan->npass == 0 || out->plan->naive || d.elem_bytes < 4;
+    return BMMC_OK;
+}
+
+int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
+                    hipStream_t stream) {
+    const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
+    int st;
+    std::vector<size_t> work;
+    for (size_t i = 0; i < arrays.size(); i++) {
+        if (arrays[i].single) {
+            st = enqueue_plan(ds, *arrays[i].plan, arrays[i].in, arrays[i].out, stream, 0);
+            if (st != BMMC_OK) return st;
+        } else {
+            if (arrays[i].plan->npass == 2 && !arrays[i].scratch)
+                return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");
+            work.push_back(i);
+        }
+    }
+    if (work.empty()) return BMMC_OK;
+
+    // Queue order.  0: two-pass arrays largest first, then one-pass arrays,
+    // then the second passes; 1: input order; 2: as 0, but the second pass
+    // of each array is queued a few arrays after its first pass, while its
+    // scratch is still warm in the last-level cache.
+    if (o.order == 0 || o.order == 2)
+        std::stable_sort(work.begin(), work.end(), [&](size_t x, size_t y) {
+            const bool px = arrays[x].plan->npass == 2, py = arrays[y].plan->npass == 2;
+            if (px != py) return px;
+            return arrays[x].bytes > arrays[y].bytes;
+        });
+
+    size_t npasses = 0, ncounters = 0, nitems = 0;
+    for (size_t a : work) {
+        const Plan& p = *arrays[a].plan;
+        npasses += p.npass;
+        if (p.npass == 2) ncounters++;
+        for (int k = 0; k < p.npass; k++) nitems += ((1u << p.pass[k].tab.ntb) + chunk - 1) / chunk;
+    }
+    BatchState* bs = batch_state(stream, ds->device);
+    st = ensure_capacity(bs, npasses, nitems, ncounters);
+    if (st != BMMC_OK) return st;
+    if (bs->staged) {
+        hipError_t e = hipEventSynchronize(bs->staged);  // staging buffer free again
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
+    uint8_t* h = (uint8_t*)bs->host;
+    BatchPass* hp = (BatchPass*)(h + L.passes_off);
+    BatchItem* hi = (BatchItem*)(h + L.items_off);
+
+    // Pass table.
+    uint32_t pidx = 0;
+    int32_t counter = 0;
+    std::vector<uint32_t> first_pass(arrays.size(), 0);
+    std::vector<int32_t> counter_of(arrays.size(), -1);
+    double moved = 0;
+    for (size_t a : work) {
+        const BatchArray& ba = arrays[a];
+        const Plan& p = *ba.plan;
+        first_pass[a] = pidx;
+        for (int k = 0; k < p.npass; k++) {
+            BatchPass& bp = hp[pidx++];
+            std::memset(&bp, 0, sizeof(bp));
+            bp.in = (k == 0) ? ba.in : ba.scratch;
+            bp.out = (k == p.npass - 1) ? ba.out : ba.scratch;
+            bp.w = (uint32_t)p.w;
+            bp.tab = p.pass[k].tab;
+        }
+        if (p.npass == 2) counter_of[a] = counter++;
+        moved += 2.0 * (double)ba.bytes;
+    }
+    // Work items: ranges of `chunk` tiles.
+    size_t ni = 0;
+    auto emit = [&](size_t a, int k) {
+        const Plan& p = *arrays[a].plan;
+        const uint32_t ntiles = 1u << p.pass[k].tab.ntb;
+        for (uint32_t t0 = 0; t0 < ntiles; t0 += chunk) {
+            BatchItem& it = hi[ni++];
+            std::memset(&it, 0, sizeof(it));
+            it.pass = first_pass[a] + (uint32_t)k;
+            it.tile_begin = t0;
+            it.tile_end = std::min(ntiles, t0 + chunk);
+            it.wait_on = -1;
+            it.signal = -1;
+            if (p.npass == 2) {
+                if (k == 0) {
+                    it.signal = counter_of[a];
+                } else {
+                    it.wait_on = counter_of[a];
+                    it.wait_count = 1u << p.pass[0].tab.ntb;
+                }
+            }
+        }
+    };
+    if (o.order == 2) {
+        const size_t lag = 4;
+        std::vector<size_t> pending;
+        for (size_t a : work) {
+            emit(a, 0);
+            if (arrays[a].plan->npass == 2) pending.push_back(a);
+            if (pending.size() > lag) {
+                emit(pending.front(), 1);
+                pending.erase(pending.begin());
+            }
+        }
+        for (size_t a : pending) emit(a, 1);
+    } else {
+        for (size_t a : work) emit(a, 0);
+        for (size_t a : work)
+            if (arrays[a].plan->npass == 2) emit(a, 1);
+    }
+    *(uint32_t*)h = (uint32_t)ni;
+
+    // Upload only what is used, then launch.
+    hipError_t e = hipMemcpyAsync(bs->dev, bs->host, L.passes_off + pidx * sizeof(BatchPass),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((uint8_t*)bs->dev + L.items_off, h + L.items_off, ni * sizeof(BatchItem),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch table)");
+    if (!bs->staged) hipEventCreateWithFlags(&bs->staged, hipEventDisableTiming);
+    hipEventRecord(bs->staged, stream);
+
+    const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
+                                           : (uint32_t)(ds->cu_count * batched_occupancy());
+    const uint32_t spin = 1u << 26;  // each spin sleeps: a bound of about a minute
+    LaunchScope ls(ds, stream, "k_batched", moved);
+    if (o.use_graph >= 0) {
+        st = build_graph(bs, grid, spin);
+        if (st != BMMC_OK) return st;
+        e = hipGraphLaunch(bs->exec, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        uint8_t* d = (uint8_t*)bs->dev;
+        uint32_t* counters = (uint32_t*)(d + L.counters_off);
+        e = launch_zero(counters, (uint32_t)bs->cap_counters + 2, stream);
+        if (e == hipSuccess)
+            e = launch_batched((const BatchPass*)(d + L.passes_off), (const BatchItem*)(d + L.items_off),
+                               (const uint32_t*)d, counters, counters + bs->cap_counters,
+                               counters + bs->cap_counters + 1, grid, spin, stream);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    return BMMC_OK;
+}
+
+int read_batched_status(DeviceState* ds, hipStream_t stream, int* timed_out) {
+    BatchState* bs = batch_state(stream, ds->device);
+    if (timed_out) *timed_out = 0;
+    if (!bs->dev) return BMMC_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
+    uint32_t v = 0;
+    e = hipMemcpy(&v, (uint8_t*)bs->dev + L.counters_off + (bs->cap_counters + 1) * sizeof(uint32_t),
+                  sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch status)");
+    if (timed_out) *timed_out = v ? 1 : 0;
+    return BMMC_OK;
+}
+
+// Signature of a batch for the tuning cache: count and a histogram of
+// (n, width) pairs.
+uint64_t batch_signature(const bmmc_desc_t* descs, int count) {
+    uint64_t hist[33 * 5] = {};
+    for (int i = 0; i < count; i++) {
+        const int w = descs[i].elem_bytes;
+        const int wi = w == 1 ? 0 : w == 2 ? 1 : w == 4 ? 2 : w == 8 ? 3 : 4;
+        const int n = descs[i].n < 0 ? 0 : descs[i].n > 32 ? 32 : descs[i].n;
+        hist[n * 5 + wi]++;
+    }
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ (uint64_t)count;
+    for (int k = 0; k < 33 * 5; k++) {
+        h ^= hist[k] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    }
+    return h;
+}
+
+}  // namespace bmmc
+
+using namespace bmmc;
+
+extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, const bmmc_batch_options_t* opts,
+                                       void* stream_) {
+    int st = batch_validate(descs, count);
+    if (st != BMMC_OK) return st;
+    if (count == 0) return BMMC_OK;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    bmmc_batch_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    else tuned_batch_options(batch_signature(descs, count), &o);
+
+    std::vector<BatchArray> arrays(count);
+    size_t scratch_total = 0;
+    std::vector<size_t> offs(count, 0);
+    for (int i = 0; i < count; i++) {
+        st = plan_batch_array(ds, descs[i], o.method, &arrays[i]);
+        if (st != BMMC_OK) return set_error(st, "array %d: %s", i, bmmc_last_error());
+        if (!arrays[i].single && arrays[i].plan->npass == 2) {
+            offs[i] = scratch_total;
+            scratch_total += (arrays[i].bytes + 255) / 256 * 256;
+        }
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    if (scratch_total) {
+        void* scratch = nullptr;
+        st = get_scratch(ds, stream, scratch_total, &scratch);
+        if (st != BMMC_OK) return st;
+        for (int i = 0; i < count; i++)
+            if (!arrays[i].single && arrays[i].plan->npass == 2) arrays[i].scratch = (uint8_t*)scratch + offs[i];
+    }
+    return enqueue_batched(ds, arrays, o, stream);
+}
+
+extern "C" int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream) {
+    return bmmc_permute_batched_ex(descs, count, nullptr, stream);
+}
+
+// Wait for the stream and report whether the last batched launch on it had to
+// give up a wait (1) or not (0).
+extern "C" int bmmc_batched_status(void* stream, int* timed_out) {
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    return read_batched_status(ds, (hipStream_t)stream, timed_out);
+}

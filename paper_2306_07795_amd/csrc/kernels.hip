@@ -1,0 +1,385 @@
+// gfx950 kernels for BMMC permutations: the LDS-staged tiled pass, the naive
+// direct-index kernel, the vector copy and the batched persistent kernel.
+//
+// Every index computation is XOR-linear (see pass.hpp): a lane's input and
+// output addresses are a per-tile scalar part XOR a per-thread part computed
+// once XOR a compile-time-selected per-iteration part, so the per-element cost
+// is one XOR and one shift whatever the matrix.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace bmmc {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int W> struct ElemT;
+template <> struct ElemT<1> { using T = uint8_t; };
+template <> struct ElemT<2> { using T = uint16_t; };
+template <> struct ElemT<4> { using T = uint32_t; };
+template <> struct ElemT<8> { using T = uint64_t; };
+template <> struct ElemT<16> { using T = u32x4; };
+
+// 16 bytes seen either as one vector or as 16/W elements.
+template <int W>
+union Vec16 {
+    u32x4 v;
+    typename ElemT<W>::T e[16 / W];
+};
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// XOR of tab[BASE + k] over the set bits k of a compile-time value.
+template <int BASE, int NBITS>
+__device__ __forceinline__ uint32_t lin_const(const uint32_t* tab, uint32_t v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < NBITS; k++)
+        if ((v >> k) & 1u) r ^= tab[BASE + k];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// One tile of a pass (paper, Section 4.1 kernel with the tiled-BMMC output
+// address of Section 5.1 and the iterations of Section 4.3):
+//   read phase : each thread loads ITERS 16-byte vectors, each lying in one
+//                contiguous run of the input, and scatters their elements to
+//                LDS slots F(v);
+//   barrier;
+//   write phase: each thread gathers the elements of ITERS output vectors from
+//                LDS slots G(u) and stores them to contiguous output runs.
+// The slot of a thread's element e of vector `it` is
+//   s = it * NT * VEC + tid * VEC + e.
+// Slots at or above 2^d do not exist when the array is smaller than the tile.
+// ---------------------------------------------------------------------------
+template <int W, int NT, int ITERS>
+struct TileCtx {
+    using E = typename ElemT<W>::T;
+    static constexpr int VEC = 16 / W;
+    static constexpr int LV = ilog2(VEC);
+    static constexpr int LT = ilog2(NT);
+    static constexpr int LI = ilog2(ITERS);
+    static constexpr int D = LV + LT + LI;
+
+    uint32_t xt, ft, yt, gt;  // per-thread parts
+    uint32_t vlim;            // valid vector slots
+
+    __device__ __forceinline__ void init(const PassTables& P, uint32_t tid) {
+        xt = ft = yt = gt = 0;
+#pragma unroll
+        for (int k = 0; k < LT; k++) {
+            const uint32_t m = 0u - ((tid >> k) & 1u);
+            xt ^= P.X[LV + k] & m;
+            ft ^= P.F[LV + k] & m;
+            yt ^= P.Y[LV + k] & m;
+            gt ^= P.G[LV + k] & m;
+        }
+        vlim = 1u << (P.d - LV);
+    }
+
+    __device__ __forceinline__ void run(const PassTables& P, const u32x4* __restrict__ in,
+                                        u32x4* __restrict__ out, E* lds, uint32_t tile,
+                                        uint32_t tid) const {
+        // Per-tile part: coset representative r, output base, LDS offset.
+        uint32_t r = 0, yb = P.c_hi, gx = P.c_lds;
+#pragma unroll
+        for (int j = 0; j < kMaxTbBits; j++) {
+            if (j < (int)P.ntb && ((tile >> j) & 1u)) {
+                r ^= P.tb_in[j];
+                yb ^= P.tb_out[j];
+                gx ^= P.tb_lds[j];
+            }
+        }
+        Vec16<W> buf[ITERS];
+#pragma unroll
+        for (int it = 0; it < ITERS; it++) {
+            if ((uint32_t)(it * NT) + tid < vlim) {
+                const uint32_t x = r ^ xt ^ lin_const<LV + LT, LI>(P.X, it);
+                buf[it].v = in[x >> LV];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < ITERS; it++) {
+            if ((uint32_t)(it * NT) + tid < vlim) {
+                const uint32_t f = ft ^ lin_const<LV + LT, LI>(P.F, it);
+#pragma unroll
+                for (int e = 0; e < VEC; e++) lds[f ^ lin_const<0, LV>(P.F, e)] = buf[it].e[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITERS; it++) {
+            if ((uint32_t)(it * NT) + tid < vlim) {
+                const uint32_t g = gt ^ gx ^ lin_const<LV + LT, LI>(P.G, it);
+                Vec16<W> o;
+#pragma unroll
+                for (int e = 0; e < VEC; e++) o.e[e] = lds[g ^ lin_const<0, LV>(P.G, e)];
+                const uint32_t y = yb ^ yt ^ lin_const<LV + LT, LI>(P.Y, it);
+                out[y >> LV] = o.v;
+            }
+        }
+        __syncthreads();
+    }
+};
+
+template <int W, int NT, int ITERS>
+__global__ void __launch_bounds__(NT)
+k_tiled(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, uint32_t ntiles) {
+    using C = TileCtx<W, NT, ITERS>;
+    __shared__ typename C::E lds[1 << C::D];
+    C ctx;
+    ctx.init(P, threadIdx.x);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        ctx.run(P, in, out, lds, tile, threadIdx.x);
+}
+
+struct TiledEntry {
+    int w, nt, iters;
+    void (*fn)(const u32x4*, u32x4*, const PassTables, uint32_t);
+};
+
+#define BMMC_TILED(W, NT, IT) {W, NT, IT, k_tiled<W, NT, IT>}
+static const TiledEntry kTiled[] = {
+    BMMC_TILED(4, 256, 4),  BMMC_TILED(4, 256, 8),  BMMC_TILED(4, 256, 2), BMMC_TILED(4, 512, 4),
+    BMMC_TILED(4, 512, 2),  BMMC_TILED(4, 1024, 2), BMMC_TILED(4, 1024, 4), BMMC_TILED(4, 256, 16),
+    BMMC_TILED(8, 256, 8),  BMMC_TILED(8, 256, 4),  BMMC_TILED(8, 512, 4), BMMC_TILED(8, 512, 8),
+    BMMC_TILED(8, 1024, 4), BMMC_TILED(8, 256, 16),
+    BMMC_TILED(16, 256, 8), BMMC_TILED(16, 256, 4), BMMC_TILED(16, 512, 4),
+    BMMC_TILED(2, 256, 2),  BMMC_TILED(2, 256, 4),
+    BMMC_TILED(1, 256, 1),  BMMC_TILED(1, 256, 4),
+};
+#undef BMMC_TILED
+
+bool tiled_kernel_available(int w, int nt, int iters) {
+    for (const auto& e : kTiled)
+        if (e.w == w && e.nt == nt && e.iters == iters) return true;
+    return false;
+}
+
+hipError_t launch_tiled(int w, int nt, int iters, const void* in, void* out, const PassTables& tab,
+                        uint32_t ntiles, uint32_t grid, hipStream_t stream) {
+    for (const auto& e : kTiled) {
+        if (e.w == w && e.nt == nt && e.iters == iters) {
+            if (grid == 0 || grid > ntiles) grid = ntiles;
+            hipLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out,
+                               tab, ntiles);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Naive kernel (the paper's naive bit-reverse kernel in the Appendix,
+// generalised to any A): each lane reads VEC consecutive elements with one
+// load and writes each to A.x XOR c.  The output index is the XOR of a
+// block-uniform part and a per-thread part (linearity of A).
+// ---------------------------------------------------------------------------
+template <int W, int VEC>
+__global__ void __launch_bounds__(256)
+k_naive(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, const NaiveArgs P) {
+    using E = typename ElemT<W>::T;
+    constexpr int LV = ilog2(VEC);
+    const uint32_t tid = threadIdx.x;
+    const uint64_t x0 = ((uint64_t)blockIdx.x * 256 + tid) << LV;
+    if ((x0 >> P.n) != 0) return;
+    const uint64_t base = (uint64_t)blockIdx.x << (LV + 8);
+    uint32_t yb = P.c;
+#pragma unroll
+    for (int j = LV + 8; j < kMaxTbBits; j++)
+        if ((base >> j) & 1u) yb ^= P.col[j];
+    uint32_t yt = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if ((tid >> k) & 1u) yt ^= P.col[LV + k];
+    E* o = reinterpret_cast<E*>(out);
+    if constexpr (VEC * W == 16) {
+        Vec16<W> v;
+        v.v = reinterpret_cast<const u32x4*>(in)[x0 >> LV];
+#pragma unroll
+        for (int e = 0; e < VEC; e++) o[yb ^ yt ^ lin_const<0, LV>(P.col, e)] = v.e[e];
+    } else {
+        o[yb ^ yt] = reinterpret_cast<const E*>(in)[x0];
+    }
+}
+
+hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs& args,
+                        hipStream_t stream) {
+    const uint64_t size = 1ull << n;
+    const int vec = 16 / w;
+    const bool vector = size >= (uint64_t)vec * 256;
+    const uint64_t lanes = vector ? size / vec : size;
+    const uint32_t grid = (uint32_t)((lanes + 255) / 256);
+    const uint8_t* i8 = (const uint8_t*)in;
+    uint8_t* o8 = (uint8_t*)out;
+#define BMMC_NAIVE(WW)                                                                            \
+    case WW:                                                                                      \
+        if (vector)                                                                               \
+            hipLaunchKernelGGL((k_naive<WW, 16 / WW>), dim3(grid), dim3(256), 0, stream, i8, o8, \
+                               args);                                                             \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_naive<WW, 1>), dim3(grid), dim3(256), 0, stream, i8, o8, args); \
+        break;
+    switch (w) {
+        BMMC_NAIVE(1)
+        BMMC_NAIVE(2)
+        BMMC_NAIVE(4)
+        BMMC_NAIVE(8)
+        BMMC_NAIVE(16)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef BMMC_NAIVE
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Copy: 4 independent 16-byte vectors per lane (Section 2.3 "copy" bound).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, uint64_t nvec) {
+    const uint64_t base = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (base + k * 256 < nvec) v[k] = in[base + k * 256];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (base + k * 256 < nvec) out[base + k * 256] = v[k];
+}
+
+__global__ void k_copy_tail(const uint8_t* in, uint8_t* out, uint32_t count) {
+    const uint32_t i = threadIdx.x;
+    if (i < count) out[i] = in[i];
+}
+
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream) {
+    const uint64_t nvec = bytes / 16;
+    if (nvec) {
+        const uint64_t grid = (nvec + 1023) / 1024;
+        hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(256), 0, stream, (const u32x4*)in,
+                           (u32x4*)out, nvec);
+    }
+    const uint32_t tail = (uint32_t)(bytes % 16);
+    if (tail)
+        hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(16), 0, stream,
+                           (const uint8_t*)in + nvec * 16, (uint8_t*)out + nvec * 16, tail);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* p, uint32_t count) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((count + 255) / 256), dim3(256), 0, stream, p, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernel.  Work items are ranges of tiles of one pass of
+// one array, taken in queue order through an atomic head.  A second-pass item
+// waits until its array's first pass has signalled all its tiles; since every
+// first-pass item of that array sits earlier in the queue, it was taken by a
+// running work-group that never waits, so the wait ends.  The wait is also
+// bounded by spin_limit: past it the kernel records an error in status[0] and
+// skips the item instead of hanging.  Every width (4, 8 or 16 bytes; the host
+// sends narrower elements through the single-array kernels) uses the same
+// 16 KiB tile buffer: 256 threads x 4 vectors x 16 bytes.
+// ---------------------------------------------------------------------------
+constexpr int kBatchNT = 256;
+constexpr int kBatchIters = 4;
+
+template <int W>
+__device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, uint32_t t1,
+                                            uint8_t* lds_bytes, uint32_t tid) {
+    using C = TileCtx<W, kBatchNT, kBatchIters>;
+    C ctx;
+    ctx.init(bp.tab, tid);
+    for (uint32_t tile = t0; tile < t1; tile++)
+        ctx.run(bp.tab, (const u32x4*)bp.in, (u32x4*)bp.out, (typename C::E*)lds_bytes, tile, tid);
+}
+
+__global__ void __launch_bounds__(kBatchNT)
+k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ items,
+          const uint32_t* __restrict__ nitems_ptr, uint32_t* counters, uint32_t* head, uint32_t* status,
+          uint32_t spin_limit) {
+    const uint32_t nitems = *nitems_ptr;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchNT * kBatchIters * 16];
+    __shared__ uint32_t s_item, s_ok;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0)
+            s_item = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t idx = s_item;
+        if (idx >= nitems) break;
+        const BatchItem item = items[idx];
+        if (item.wait_on >= 0) {
+            if (tid == 0) {
+                uint32_t spins = 0, ok = 1;
+                while (__hip_atomic_load(&counters[item.wait_on], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < item.wait_count) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > spin_limit) {
+                        ok = 0;
+                        __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!s_ok) {
+                __syncthreads();
+                continue;
+            }
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);  // see the first pass's stores
+        }
+        const BatchPass& bp = passes[item.pass];
+        switch (bp.w) {
+            case 4: batch_tiles<4>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 8: batch_tiles<8>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            default: batch_tiles<16>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+        }
+        if (item.signal >= 0) {
+            __threadfence();  // publish this thread's stores device-wide
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&counters[item.signal], item.tile_end - item.tile_begin,
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();  // s_item is rewritten next round
+    }
+}
+
+hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* nitems,
+                          uint32_t* counters, uint32_t* head, uint32_t* status, uint32_t grid,
+                          uint32_t spin_limit, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, nitems,
+                       counters, head, status, spin_limit);
+    return hipGetLastError();
+}
+
+int batched_occupancy() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched, kBatchNT, 0) != hipSuccess)
+        blocks = 4;
+    return blocks > 0 ? blocks : 1;
+}
+
+int tiled_occupancy(int w, int nt, int iters) {
+    for (const auto& e : kTiled) {
+        if (e.w == w && e.nt == nt && e.iters == iters) {
+            int blocks = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, e.fn, nt, 0) != hipSuccess)
+                return 1;
+            return blocks > 0 ? blocks : 1;
+        }
+    }
+    return 1;
+}
+
+}  // namespace bmmc

@@ -1,0 +1,52 @@
+// Launchers for the gfx950 kernels (definitions in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pass.hpp"
+
+namespace bmmc {
+
+// Column masks of A for the naive kernel: col[j] = A.e_j (0 for j >= n).
+struct NaiveArgs {
+    uint32_t n;
+    uint32_t c;
+    uint32_t col[kMaxTbBits];
+};
+
+// True when a tiled kernel exists for (w, nt, iters).
+bool tiled_kernel_available(int w, int nt, int iters);
+
+// One LDS-staged pass over `ntiles` tiles with `grid` work-groups
+// (grid-stride over tiles).  in/out are 16-byte aligned device pointers.
+hipError_t launch_tiled(int w, int nt, int iters, const void* in, void* out,
+                        const PassTables& tab, uint32_t ntiles, uint32_t grid,
+                        hipStream_t stream);
+
+// Naive kernel: 2^n elements, one 16-byte vector (or one element when
+// 2^n * w < 16 * 256) per lane, scattered element stores.
+hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs& args,
+                        hipStream_t stream);
+
+// 16-byte vector copy of `bytes` bytes (tail handled bytewise).
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream);
+
+// Batched persistent kernel (batched.hip).
+// passes / items / nitems / counters / head are device pointers; counters and
+// head must be zero at launch.  status[0] receives a nonzero code if a wait
+// timed out (the kernel then skips the item rather than hang).
+hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* nitems,
+                          uint32_t* counters, uint32_t* head, uint32_t* status,
+                          uint32_t grid, uint32_t spin_limit, hipStream_t stream);
+// Resident work-groups per CU of the batched kernel / of a tiled kernel.
+int batched_occupancy();
+int tiled_occupancy(int w, int nt, int iters);
+// Shape of the batched kernel's tile for an element width.
+inline int batched_iters() { return 4; }
+inline int batched_threads() { return 256; }
+
+// Clears `count` 32-bit words with a kernel (no memset nodes in graphs).
+hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream);
+
+}  // namespace bmmc

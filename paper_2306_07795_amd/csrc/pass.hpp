@@ -1,0 +1,64 @@
+// Tables that drive one LDS-staged pass.  Shared by the host planner and the
+// device kernels; plain data only.
+//
+// A pass moves out[T.x XOR c] = in[x] one tile at a time.  A tile is a coset
+// r XOR V of a d-dimensional subspace V of the index space (paper, Section 4.1
+// tiles and Section 5.1 tiled BMMCs; the iteration bits of Section 4.3 are
+// extra dimensions of V).  Inside a tile an element has
+//   * read coordinates v in [0, 2^d): input index  x = r XOR X(v),
+//   * write coordinates u in [0, 2^d): output index y = T.r XOR c XOR Y(u),
+// where X and Y are linear maps given by their values on the unit vectors.
+// X keeps the low `a` input bits as its first coordinates and Y the low `b`
+// output bits, so every run of 2^a read slots is a contiguous aligned run of
+// the input and every run of 2^b write slots a contiguous aligned run of the
+// output.  The element with read coordinates v sits in LDS at slot F(v); the
+// element with write coordinates u at slot G(u) = F(M^-1 u).  All maps are
+// XOR-linear, so each address is a XOR of a per-tile part, a per-thread part
+// and a per-iteration part (the amortization of Section 4.3, extended to any
+// tiled BMMC by linearity).
+#pragma once
+#include <cstdint>
+
+namespace bmmc {
+
+constexpr int kMaxTileBits = 16;  // largest tile: 2^16 elements
+constexpr int kMaxTbBits = 32;    // index math is 32-bit: n <= 32
+
+struct PassTables {
+    uint32_t n;      // index bits of the array
+    uint32_t d;      // tile bits used (d = min(n, D))
+    uint32_t ntb;    // tile-selecting bits, n - d
+    uint32_t c_hi;   // complement with its low b bits cleared
+    uint32_t c_lds;  // LDS slot offset that absorbs the low b bits of c
+    uint32_t pad_[3];
+    uint32_t X[kMaxTileBits];    // input offset of read-coordinate bit k
+    uint32_t F[kMaxTileBits];    // LDS slot of read-coordinate bit k
+    uint32_t Y[kMaxTileBits];    // output offset of write-coordinate bit k
+    uint32_t G[kMaxTileBits];    // LDS slot of write-coordinate bit k
+    uint32_t tb_in[kMaxTbBits];  // input offset of tile-index bit j
+    uint32_t tb_out[kMaxTbBits]; // output offset of tile-index bit j (low b bits cleared)
+    uint32_t tb_lds[kMaxTbBits]; // LDS offset absorbing the low b bits of T.tb_in[j]
+};
+
+// One work item of the batched persistent kernel: a range of tiles of one
+// pass of one array.
+struct BatchItem {
+    uint32_t pass;        // index into the pass table
+    uint32_t tile_begin;  // first tile
+    uint32_t tile_end;    // one past the last tile
+    int32_t wait_on;      // counter that must reach wait_count first, or -1
+    uint32_t wait_count;
+    int32_t signal;       // counter bumped by (tile_end - tile_begin) when done, or -1
+    uint32_t pad_[2];
+};
+
+// Per-pass device descriptor for the batched kernel.
+struct BatchPass {
+    const void* in;
+    void* out;
+    uint32_t w;      // element bytes
+    uint32_t pad_[3];
+    PassTables tab;
+};
+
+}  // namespace bmmc

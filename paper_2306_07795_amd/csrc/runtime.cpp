@@ -1,0 +1,432 @@
+// C entry points for planning and the single-array device path, plus the
+// runtime pieces they share (plan cache, per-stream scratch, profiling).
+#include "runtime.hpp"
+
+#include <cstdio>
+#include <cstring>
+
+#include "kernels.hpp"
+
+namespace bmmc {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return set_error(BMMC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool PlanKey::operator==(const PlanKey& o) const {
+    if (n != o.n || w != o.w || method != o.method || t != o.t || nt != o.nt || iters != o.iters ||
+        swizzle != o.swizzle || c != o.c)
+        return false;
+    for (int i = 0; i < n; i++)
+        if (rows[i] != o.rows[i]) return false;
+    return true;
+}
+
+size_t PlanKeyHash::operator()(const PlanKey& k) const {
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mixin = [&](uint64_t v) {
+        h ^= v;
+        h *= 0x100000001b3ull;
+        h ^= h >> 29;
+    };
+    mixin((uint64_t)k.n | ((uint64_t)k.w << 8) | ((uint64_t)k.method << 16) | ((uint64_t)k.t << 24) |
+          ((uint64_t)k.nt << 32) | ((uint64_t)k.iters << 48) | ((uint64_t)k.swizzle << 60));
+    mixin(k.c);
+    for (int i = 0; i < k.n; i++) mixin(k.rows[i]);
+    return (size_t)h;
+}
+
+DeviceState* device_state(int* status) {
+    static std::mutex mu;
+    static DeviceState* states[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) {
+        *status = hip_fail(e == hipSuccess ? hipErrorInvalidDevice : e, "hipGetDevice");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!states[dev]) {
+        auto* s = new DeviceState();
+        s->device = dev;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        s->cu_count = cus;
+        states[dev] = s;
+    }
+    *status = BMMC_OK;
+    return states[dev];
+}
+
+int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions& o,
+             std::shared_ptr<const Plan>* out) {
+    if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
+    if (n > 0 && !rows) return set_error(BMMC_ERR_ARG, "A_rows is NULL");
+    PlanKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.n = n;
+    key.w = w;
+    key.method = o.method;
+    key.t = o.t;
+    key.nt = o.shape.nt;
+    key.iters = o.shape.iters;
+    key.swizzle = o.swizzle;
+    key.c = c;
+    for (int i = 0; i < n; i++) key.rows[i] = rows[i];
+    {
+        std::lock_guard<std::mutex> lk(ds->mu);
+        auto it = ds->plans.find(key);
+        if (it != ds->plans.end()) {
+            *out = it->second;
+            return BMMC_OK;
+        }
+    }
+    auto plan = std::make_shared<Plan>();
+    int st = make_plan(rows, c, n, w, o, plan.get());
+    if (st != BMMC_OK) {
+        switch (st) {
+            case BMMC_ERR_SINGULAR: return set_error(st, "A is singular over F_2");
+            case BMMC_ERR_ARG: return set_error(st, "bad argument: width %d, or bits of A or c at positions >= n = %d", w, n);
+            case BMMC_ERR_RANGE: return set_error(st, "tile geometry out of range (n = %d, t = %d, w = %d)", n, o.t, w);
+            default: return set_error(st, "planner failed (%d)", st);
+        }
+    }
+    std::lock_guard<std::mutex> lk(ds->mu);
+    if (ds->plans.size() > 8192) ds->plans.clear();
+    ds->plans[key] = plan;
+    *out = plan;
+    return BMMC_OK;
+}
+
+int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out) {
+    auto& s = ds->scratch[stream];
+    if (s.bytes < bytes) {
+        if (s.ptr) {
+            // earlier work on this stream may still read the old buffer
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            hipFree(s.ptr);
+            s.ptr = nullptr;
+            s.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&s.ptr, bytes);
+        if (e != hipSuccess) {
+            s.ptr = nullptr;
+            (void)hipGetLastError();
+            return set_error(BMMC_ERR_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+        }
+        s.bytes = bytes;
+    }
+    *out = s.ptr;
+    return BMMC_OK;
+}
+
+LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes) : ds(d), stream(s) {
+    if (!ds->profiling) return;
+    ProfileEvent pe;
+    pe.name = name;
+    pe.bytes = bytes;
+    for (hipEvent_t* slot : {&pe.start, &pe.stop}) {
+        if (!ds->event_pool.empty()) {
+            *slot = ds->event_pool.back();
+            ds->event_pool.pop_back();
+        } else if (hipEventCreate(slot) != hipSuccess) {
+            return;
+        }
+    }
+    hipEventRecord(pe.start, stream);
+    ds->events.push_back(pe);
+    ev = &ds->events.back();
+}
+
+LaunchScope::~LaunchScope() {
+    if (ev) hipEventRecord(ds->events.back().stop, stream);
+}
+
+PlanOptions plan_options(const bmmc_options_t* o, int w) {
+    PlanOptions p;
+    p.shape = default_shape(w);
+    if (!o) return p;
+    p.method = o->method;
+    p.t = o->t;
+    p.swizzle = o->swizzle < 0 ? 0 : 1;
+    if (o->threads > 0) p.shape.nt = o->threads;
+    if (o->iters > 0) p.shape.iters = o->iters;
+    return p;
+}
+
+// Name of the tiled kernel instance, shared by both passes of a plan.
+static void kernel_name(char* buf, size_t len, const Plan& p) {
+    snprintf(buf, len, "k_tiled<%d,%d,%d>", p.w, p.shape.nt, p.shape.iters);
+}
+
+int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
+                 uint32_t grid) {
+    const size_t bytes = ((size_t)1 << plan.n) * (size_t)plan.w;
+    hipError_t e;
+    if (plan.npass == 0) {
+        LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
+        e = launch_copy(in, out, bytes, stream);
+        return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
+    }
+    if (plan.naive) {
+        NaiveArgs na;
+        std::memset(&na, 0, sizeof(na));
+        na.n = (uint32_t)plan.n;
+        na.c = (uint32_t)plan.c;
+        for (int j = 0; j < plan.n; j++) na.col[j] = (uint32_t)plan.A.col(j);
+        LaunchScope ls(ds, stream, "k_naive", 2.0 * bytes);
+        e = launch_naive(plan.w, plan.n, in, out, na, stream);
+        return e == hipSuccess ? BMMC_OK : hip_fail(e, "naive launch");
+    }
+    const KernelShape& ks = plan.shape;
+    if (!tiled_kernel_available(plan.w, ks.nt, ks.iters))
+        return set_error(BMMC_ERR_RANGE, "no tiled kernel for w=%d threads=%d iters=%d", plan.w, ks.nt, ks.iters);
+    void* mid = nullptr;
+    if (plan.npass == 2) {
+        int st = get_scratch(ds, stream, bytes, &mid);
+        if (st != BMMC_OK) return st;
+    }
+    char name[64];
+    for (int k = 0; k < plan.npass; k++) {
+        const PassTables& tab = plan.pass[k].tab;
+        const void* src = (k == 0) ? in : mid;
+        void* dst = (k == plan.npass - 1) ? out : mid;
+        const uint32_t ntiles = 1u << tab.ntb;
+        kernel_name(name, sizeof(name), plan);
+        LaunchScope ls(ds, stream, name, 2.0 * bytes);
+        e = launch_tiled(plan.w, ks.nt, ks.iters, src, dst, tab, ntiles, grid, stream);
+        if (e != hipSuccess) return hip_fail(e, "tiled launch");
+    }
+    return BMMC_OK;
+}
+
+int validate_buffers(const void* in, const void* out, size_t bytes) {
+    if (!in || !out) return set_error(BMMC_ERR_ARG, "in/out must not be NULL");
+    if (((uintptr_t)in | (uintptr_t)out) & 15u) return set_error(BMMC_ERR_ARG, "in/out must be 16-byte aligned");
+    const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+    if (a < b + bytes && b < a + bytes) return set_error(BMMC_ERR_ALIAS, "in and out overlap");
+    return BMMC_OK;
+}
+
+static void fill_public_plan(const Plan& p, bmmc_plan_t* out) {
+    std::memset(out, 0, sizeof(*out));
+    out->n = p.n;
+    out->t = p.t;
+    out->elem_bytes = p.w;
+    out->nfactors = p.npass;
+    for (int k = 0; k < p.npass && k < 2; k++) {
+        const PassPlan& pp = p.pass[k];
+        if (p.naive) {
+            for (int i = 0; i < p.n; i++) out->rows[k][i] = p.A.r[i];
+            out->c[k] = p.c;
+            continue;
+        }
+        for (int i = 0; i < p.n; i++) out->rows[k][i] = pp.T.r[i];
+        out->c[k] = pp.c;
+        out->col_mask[k] = pp.col_mask;
+        out->tile_rows_mask[k] = pp.row_mask;
+        out->iter_mask[k] = pp.iter_mask;
+        out->tb_mask[k] = pp.tb_mask;
+        out->n_over[k] = pp.n_over;
+        out->tile_bits[k] = pp.d;
+        out->coordinate[k] = pp.coordinate ? 1 : 0;
+        out->lds_conflict_score[k] = pp.lds_score;
+    }
+}
+
+}  // namespace bmmc
+
+using namespace bmmc;
+
+extern "C" {
+
+const char* bmmc_strerror(int status) {
+    switch (status) {
+        case BMMC_OK: return "ok";
+        case BMMC_ERR_ARG: return "invalid argument";
+        case BMMC_ERR_SINGULAR: return "matrix is singular over F_2";
+        case BMMC_ERR_RANGE: return "size or tile parameter out of range";
+        case BMMC_ERR_ALIAS: return "input and output overlap";
+        case BMMC_ERR_NOMEM: return "out of memory";
+        case BMMC_ERR_HIP: return "HIP runtime error";
+        case BMMC_ERR_INTERNAL: return "internal planner error";
+        case BMMC_ERR_NOTFOUND: return "unknown handle or ticket";
+        case BMMC_ERR_BUSY: return "not finished";
+        default: return "unknown status";
+    }
+}
+
+const char* bmmc_last_error(void) { return g_last_error.c_str(); }
+
+int bmmc_version(void) { return BMMC_VERSION; }
+
+int bmmc_is_tiled(const uint64_t* A_rows, int n, int t, uint64_t* rows_mask_out) {
+    if (n < 0 || n > 64 || t < 0 || t > n) return set_error(BMMC_ERR_RANGE, "n or t out of range");
+    if (n > 0 && !A_rows) return set_error(BMMC_ERR_ARG, "A_rows is NULL");
+    BitMat A;
+    A.n = n;
+    for (int i = 0; i < n; i++) A.r[i] = A_rows[i] & low_mask(n);
+    if (rank(A) != n) return set_error(BMMC_ERR_SINGULAR, "A is singular over F_2");
+    const uint64_t S = tiled_row_mask(A, t);
+    if (rows_mask_out) *rows_mask_out = S;
+    return popcount64(S) == t ? 1 : 0;
+}
+
+int bmmc_factorize_t(const uint64_t* A_rows, uint64_t c, int n, int t, int elem_bytes,
+                     bmmc_plan_t* plan_out) {
+    if (!plan_out) return set_error(BMMC_ERR_ARG, "plan_out is NULL");
+    PlanOptions o;
+    int w = elem_bytes > 0 ? elem_bytes : 4;
+    o.shape = default_shape(w);
+    o.t = t;
+    Plan p;
+    int st = make_plan(A_rows, c, n, w, o, &p);
+    if (st != BMMC_OK) return set_error(st, "planning failed: %s", bmmc_strerror(st));
+    fill_public_plan(p, plan_out);
+    return BMMC_OK;
+}
+
+int bmmc_plan_ex(const uint64_t* A_rows, uint64_t c, int n, int elem_bytes, const bmmc_options_t* opts,
+                 bmmc_plan_t* plan_out) {
+    if (!plan_out) return set_error(BMMC_ERR_ARG, "plan_out is NULL");
+    if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
+        return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
+    PlanOptions o = plan_options(opts, elem_bytes);
+    Plan p;
+    int st = make_plan(A_rows, c, n, elem_bytes, o, &p);
+    if (st != BMMC_OK) return set_error(st, "planning failed: %s", bmmc_strerror(st));
+    fill_public_plan(p, plan_out);
+    return BMMC_OK;
+}
+
+int bmmc_factorize_ulp(const uint64_t* A_rows, int n, uint64_t* U, uint64_t* L, uint64_t* P, uint64_t* T1,
+                       uint64_t* T2) {
+    if (n < 1 || n > 64) return set_error(BMMC_ERR_RANGE, "n = %d outside [1, 64]", n);
+    if (!A_rows) return set_error(BMMC_ERR_ARG, "A_rows is NULL");
+    BitMat A;
+    A.n = n;
+    for (int i = 0; i < n; i++) {
+        if (A_rows[i] & ~low_mask(n)) return set_error(BMMC_ERR_ARG, "row %d has bits at positions >= n", i);
+        A.r[i] = A_rows[i];
+    }
+    BitMat u, l, pm, t1, t2;
+    if (!factorize_ulp(A, &u, &l, &pm, &t1, &t2)) return set_error(BMMC_ERR_SINGULAR, "A is singular over F_2");
+    for (int i = 0; i < n; i++) {
+        if (U) U[i] = u.r[i];
+        if (L) L[i] = l.r[i];
+        if (P) P[i] = pm.r[i];
+        if (T1) T1[i] = t1.r[i];
+        if (T2) T2[i] = t2.r[i];
+    }
+    return BMMC_OK;
+}
+
+int bmmc_factorize(const uint64_t* A_rows, uint64_t c, int n, bmmc_plan_t* plan_out) {
+    return bmmc_factorize_t(A_rows, c, n, 0, 4, plan_out);
+}
+
+int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                    int elem_bytes, const bmmc_options_t* opts, void* stream) {
+    if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
+    if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
+        return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
+    const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
+    int st = validate_buffers(in, out, bytes);
+    if (st != BMMC_OK) return st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    bmmc_options_t tuned;
+    if (!opts && tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, &tuned)) opts = &tuned;
+    PlanOptions po = plan_options(opts, elem_bytes);
+    std::shared_ptr<const Plan> plan;
+    st = get_plan(ds, A_rows, c, n, elem_bytes, po, &plan);
+    if (st != BMMC_OK) return st;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, opts ? (uint32_t)opts->grid : 0);
+}
+
+int bmmc_permute(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                 int elem_bytes, void* stream) {
+    return bmmc_permute_ex(in, out, n, A_rows, c, elem_bytes, nullptr, stream);
+}
+
+int bmmc_permute_naive(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                       int elem_bytes, void* stream) {
+    bmmc_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.method = BMMC_METHOD_NAIVE;
+    return bmmc_permute_ex(in, out, n, A_rows, c, elem_bytes, &o, stream);
+}
+
+int bmmc_copy(const void* in, void* out, size_t bytes, void* stream) {
+    int st = validate_buffers(in, out, bytes);
+    if (st != BMMC_OK) return st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    LaunchScope ls(ds, (hipStream_t)stream, "k_copy", 2.0 * (double)bytes);
+    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
+}
+
+int bmmc_profile_begin(void) {
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    ds->profiling = true;
+    ds->events.clear();
+    ds->events.reserve(1 << 16);
+    return BMMC_OK;
+}
+
+int bmmc_profile_end(bmmc_kernel_stat_t* out, int max) {
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    ds->profiling = false;
+    std::vector<bmmc_kernel_stat_t> acc;
+    for (auto& ev : ds->events) {
+        float ms = 0.f;
+        if (hipEventSynchronize(ev.stop) == hipSuccess) hipEventElapsedTime(&ms, ev.start, ev.stop);
+        bmmc_kernel_stat_t* slot = nullptr;
+        for (auto& a : acc)
+            if (ev.name == a.name) slot = &a;
+        if (!slot) {
+            bmmc_kernel_stat_t s;
+            std::memset(&s, 0, sizeof(s));
+            snprintf(s.name, sizeof(s.name), "%s", ev.name.c_str());
+            acc.push_back(s);
+            slot = &acc.back();
+        }
+        slot->launches++;
+        slot->total_ms += ms;
+        slot->bytes += ev.bytes;
+        ds->event_pool.push_back(ev.start);
+        ds->event_pool.push_back(ev.stop);
+    }
+    ds->events.clear();
+    int k = 0;
+    for (auto& a : acc) {
+        if (k >= max) break;
+        out[k++] = a;
+    }
+    return k;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Runtime shared by the C entry points: per-device state, plan cache,
+// per-stream scratch, error reporting and launch profiling.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "bmmc.h"
+#include "plan.hpp"
+
+namespace bmmc {
+
+int set_error(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+struct PlanKey {
+    int n, w, method, t, nt, iters, swizzle;
+    uint64_t c;
+    uint64_t rows[kMaxBits];
+    bool operator==(const PlanKey& o) const;
+};
+struct PlanKeyHash {
+    size_t operator()(const PlanKey& k) const;
+};
+
+struct ProfileEvent {
+    std::string name;
+    double bytes;
+    hipEvent_t start, stop;
+};
+
+struct DeviceState {
+    int device = 0;
+    int cu_count = 0;
+    std::mutex mu;
+    std::unordered_map<PlanKey, std::shared_ptr<const Plan>, PlanKeyHash> plans;
+    struct Scratch {
+        void* ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::unordered_map<hipStream_t, Scratch> scratch;
+    bool profiling = false;
+    std::vector<ProfileEvent> events;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// State of the current device (created on first use).
+DeviceState* device_state(int* status);
+
+// Cached plan for (A, c, n, w, options).
+int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions& o,
+             std::shared_ptr<const Plan>* out);
+
+// Scratch of at least `bytes` for `stream` (caller holds ds->mu).
+int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out);
+
+// Record profiling events around a launch when profiling is on (caller holds ds->mu).
+struct LaunchScope {
+    DeviceState* ds;
+    hipStream_t stream;
+    ProfileEvent* ev = nullptr;
+    LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes);
+    ~LaunchScope();
+};
+
+// Plan options from the public option struct.
+PlanOptions plan_options(const bmmc_options_t* o, int w);
+
+// Enqueue the passes of a plan (caller holds ds->mu).
+int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
+                 uint32_t grid);
+
+int validate_buffers(const void* in, const void* out, size_t bytes);
+
+// One array of a batched launch.
+struct BatchArray {
+    const void* in = nullptr;
+    void* out = nullptr;
+    void* scratch = nullptr;  // 2^n * w bytes for two-pass plans
+    size_t bytes = 0;
+    bool single = false;      // runs through the single-array kernels
+    std::shared_ptr<const Plan> plan;
+};
+
+int batch_validate(const bmmc_desc_t* descs, int count);
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out);
+// Enqueue one batched launch (caller holds ds->mu).
+int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
+                    hipStream_t stream);
+int read_batched_status(DeviceState* ds, hipStream_t stream, int* timed_out);
+uint64_t batch_signature(const bmmc_desc_t* descs, int count);
+
+// Tuning cache lookups (tune.cpp); false when nothing is cached.
+bool tuned_options(int n, int w, int method, bmmc_options_t* out);
+bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out);
+
+}  // namespace bmmc

@@ -1,0 +1,503 @@
+// Serving loop: permutation requests arrive over time, are planned, admitted
+// against an HBM budget and run with continuous batching.
+//
+//  * submit() queues a request with its arrival time (the caller's clock is
+//    bmmc_server_now_ns; a future arrival time is honoured, so a client can
+//    hand over a whole open-loop schedule at once);
+//  * a planner thread plans requests as they arrive;
+//  * the dispatcher admits planned requests in arrival order while their
+//    footprint (input + output + scratch) fits the budget, and whenever one
+//    of its K streams is free it launches every admitted request as one
+//    batched persistent launch on that stream, so launches overlap on the
+//    device and requests that arrive while others run join the next launch;
+//  * completions are seen by polling each stream's event; latency is
+//    completion minus arrival.
+// Outputs and scratch come from one device arena of `budget` bytes managed as
+// a buddy allocator (all sizes are powers of two).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <queue>
+#include <set>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace bmmc {
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Buddy allocator over [0, 2^top) in blocks of 2^min_log bytes.
+class Buddy {
+   public:
+    void init(int top_log, int min_log) {
+        top_ = top_log;
+        min_ = min_log;
+        free_.assign(top_ + 1, {});
+        free_[top_].insert(0);
+    }
+    // Offset of a block of at least `bytes`, or -1.
+    int64_t alloc(size_t bytes) {
+        int k = min_;
+        while (((size_t)1 << k) < bytes) k++;
+        if (k > top_) return -1;
+        int j = k;
+        while (j <= top_ && free_[j].empty()) j++;
+        if (j > top_) return -1;
+        int64_t off = *free_[j].begin();
+        free_[j].erase(free_[j].begin());
+        while (j > k) {
+            j--;
+            free_[j].insert(off + ((int64_t)1 << j));
+        }
+        size_[off] = k;
+        return off;
+    }
+    void release(int64_t off) {
+        auto it = size_.find(off);
+        if (it == size_.end()) return;
+        int k = it->second;
+        size_.erase(it);
+        while (k < top_) {
+            const int64_t buddy = off ^ ((int64_t)1 << k);
+            auto f = free_[k].find(buddy);
+            if (f == free_[k].end()) break;
+            free_[k].erase(f);
+            off = std::min(off, buddy);
+            k++;
+        }
+        free_[k].insert(off);
+    }
+
+   private:
+    int top_ = 0, min_ = 12;
+    std::vector<std::set<int64_t>> free_;
+    std::unordered_map<int64_t, int> size_;
+};
+
+enum ReqState { kPending = 0, kPlanned, kAdmitted, kRunning, kDone, kFailed };
+
+struct Request {
+    int64_t ticket = 0;
+    bmmc_desc_t desc{};
+    uint64_t rows[64] = {};
+    int64_t arrival_ns = 0;
+    int64_t done_ns = 0;
+    std::shared_ptr<const Plan> plan;
+    size_t bytes = 0;
+    size_t footprint = 0;
+    int64_t out_off = -1, scratch_off = -1;
+    void* out = nullptr;
+    void* scratch = nullptr;
+    int state = kPending;
+    int status = BMMC_OK;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Request*> reqs;
+    bool busy = false;
+};
+
+struct ArrivalLater {
+    bool operator()(const Request* a, const Request* b) const { return a->arrival_ns > b->arrival_ns; }
+};
+
+}  // namespace
+
+struct Server {
+    bmmc_server_options_t opt{};
+    int device = 0;
+    DeviceState* ds = nullptr;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    Buddy buddy;
+    int64_t in_use = 0, peak = 0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::priority_queue<Request*, std::vector<Request*>, ArrivalLater> future;  // not arrived yet
+    std::deque<Request*> to_plan, ready, admitted;
+    std::unordered_map<int64_t, Request*> table;
+    std::vector<Slot> slots;
+    int64_t next_ticket = 1;
+    bool stop = false;
+    std::thread planner, dispatcher;
+
+    // statistics
+    int64_t submitted = 0, completed = 0, rejected = 0, batches = 0;
+    double bytes_moved = 0, batch_reqs = 0;
+    int64_t first_arrival = -1, last_done = 0;
+    std::vector<double> latencies_ms;
+
+    void plan_loop();
+    void dispatch_loop();
+    void finish_slot(Slot& s, int64_t t);
+    bool try_admit(Request* r);
+    void free_request_memory(Request* r, bool keep_out);
+};
+
+void Server::free_request_memory(Request* r, bool keep_out) {
+    if (r->scratch_off >= 0) {
+        buddy.release(r->scratch_off);
+        r->scratch_off = -1;
+        r->scratch = nullptr;
+    }
+    if (!keep_out && r->out_off >= 0) {
+        buddy.release(r->out_off);
+        r->out_off = -1;
+    }
+}
+
+bool Server::try_admit(Request* r) {
+    const bool two = !r->plan->naive && r->plan->npass == 2;
+    r->footprint = r->bytes * (two ? 3 : 2);  // input + output (+ scratch)
+    if (in_use + (int64_t)r->footprint > opt.budget_bytes) return false;
+    if (opt.own_outputs) {
+        r->out_off = buddy.alloc(r->bytes);
+        if (r->out_off < 0) return false;
+        r->out = (uint8_t*)arena + r->out_off;
+        r->desc.out = r->out;
+    }
+    if (two) {
+        r->scratch_off = buddy.alloc(r->bytes);
+        if (r->scratch_off < 0) {
+            if (r->out_off >= 0) buddy.release(r->out_off);
+            r->out_off = -1;
+            return false;
+        }
+        r->scratch = (uint8_t*)arena + r->scratch_off;
+    }
+    in_use += (int64_t)r->footprint;
+    peak = std::max(peak, in_use);
+    r->state = kAdmitted;
+    return true;
+}
+
+void Server::plan_loop() {
+    hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        cv_work.wait(lk, [&] { return stop || !to_plan.empty(); });
+        if (stop) return;
+        Request* r = to_plan.front();
+        to_plan.pop_front();
+        lk.unlock();
+        BatchArray ba;
+        int st = plan_batch_array(ds, r->desc, opt.method, &ba);
+        lk.lock();
+        if (st != BMMC_OK) {
+            r->status = st;
+            r->state = kFailed;
+            r->done_ns = now_ns();
+            rejected++;
+            cv_done.notify_all();
+            continue;
+        }
+        r->plan = ba.plan;
+        r->state = kPlanned;
+        ready.push_back(r);
+        cv_work.notify_all();
+    }
+}
+
+void Server::finish_slot(Slot& s, int64_t t) {
+    for (Request* r : s.reqs) {
+        r->done_ns = t;
+        r->state = kDone;
+        const double lat = (double)(t - r->arrival_ns) * 1e-6;
+        latencies_ms.push_back(lat);
+        completed++;
+        bytes_moved += 2.0 * (double)r->bytes;
+        last_done = std::max(last_done, t);
+        // The input stops counting once read; the output stays until the
+        // client releases it (own_outputs == 1) or is dropped now (== 2).
+        const bool keep_out = opt.own_outputs == 1;
+        free_request_memory(r, keep_out);
+        in_use -= (int64_t)(r->footprint - (keep_out ? r->bytes : 0));
+        r->footprint = keep_out ? r->bytes : 0;
+        if (opt.own_outputs == 2) {  // nobody will poll: forget the request
+            table.erase(r->ticket);
+            delete r;
+        }
+    }
+    s.reqs.clear();
+    s.busy = false;
+}
+
+void Server::dispatch_loop() {
+    hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop) {
+        bool progress = false;
+        const int64_t t = now_ns();
+        // arrivals
+        while (!future.empty() && future.top()->arrival_ns <= t) {
+            to_plan.push_back(future.top());
+            future.pop();
+            cv_work.notify_all();
+        }
+        // completions
+        for (Slot& s : slots) {
+            if (s.busy && hipEventQuery(s.done) == hipSuccess) {
+                finish_slot(s, now_ns());
+                progress = true;
+                cv_done.notify_all();
+            }
+        }
+        // admission in arrival order
+        while (!ready.empty() && try_admit(ready.front())) {
+            admitted.push_back(ready.front());
+            ready.pop_front();
+            progress = true;
+        }
+        // launch everything admitted on a free stream
+        if (!admitted.empty()) {
+            for (Slot& s : slots) {
+                if (s.busy) continue;
+                size_t take = admitted.size();
+                if (opt.max_batch > 0) take = std::min(take, (size_t)opt.max_batch);
+                std::vector<BatchArray> arrays(take);
+                for (size_t i = 0; i < take; i++) {
+                    Request* r = admitted[i];
+                    BatchArray& ba = arrays[i];
+                    ba.in = r->desc.in;
+                    ba.out = r->desc.out;
+                    ba.scratch = r->scratch;
+                    ba.bytes = r->bytes;
+                    ba.plan = r->plan;
+                    ba.single = r->plan->npass == 0 || r->plan->naive || r->desc.elem_bytes < 4;
+                    r->state = kRunning;
+                    s.reqs.push_back(r);
+                }
+                admitted.erase(admitted.begin(), admitted.begin() + take);
+                bmmc_batch_options_t bo;
+                std::memset(&bo, 0, sizeof(bo));
+                bo.method = opt.method;
+                int st;
+                {
+                    std::lock_guard<std::mutex> dl(ds->mu);
+                    st = enqueue_batched(ds, arrays, bo, s.stream);
+                }
+                if (st == BMMC_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = BMMC_ERR_HIP;
+                if (st != BMMC_OK) {
+                    for (Request* r : s.reqs) {
+                        r->status = st;
+                        r->state = kFailed;
+                        r->done_ns = now_ns();
+                        free_request_memory(r, false);
+                        in_use -= (int64_t)r->footprint;
+                        r->footprint = 0;
+                        rejected++;
+                    }
+                    s.reqs.clear();
+                    cv_done.notify_all();
+                } else {
+                    s.busy = true;
+                    batches++;
+                    batch_reqs += (double)take;
+                }
+                progress = true;
+                break;
+            }
+        }
+        if (!progress) {
+            // Sleep until new work arrives or briefly, to poll the streams.
+            int64_t wait_ns = 20000;
+            if (!future.empty()) wait_ns = std::min<int64_t>(wait_ns, std::max<int64_t>(0, future.top()->arrival_ns - now_ns()));
+            bool any_busy = false;
+            for (Slot& s : slots) any_busy |= s.busy;
+            if (!any_busy && future.empty() && ready.empty() && to_plan.empty())
+                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            else if (wait_ns > 0)
+                cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+        }
+    }
+}
+
+}  // namespace bmmc
+
+using namespace bmmc;
+
+extern "C" int64_t bmmc_server_now_ns(void) { return now_ns(); }
+
+extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out) {
+    if (!opts || !handle_out) return set_error(BMMC_ERR_ARG, "opts/handle_out is NULL");
+    if (opts->budget_bytes < (1 << 20)) return set_error(BMMC_ERR_ARG, "budget below 1 MiB");
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    auto* s = new Server();
+    s->opt = *opts;
+    if (s->opt.streams <= 0) s->opt.streams = 4;
+    if (s->opt.streams > 16) s->opt.streams = 16;
+    s->ds = ds;
+    s->device = ds->device;
+    // Arena: the largest power of two not above the budget, for outputs and scratch.
+    int top = 20;
+    while (((int64_t)1 << (top + 1)) <= s->opt.budget_bytes && top < 46) top++;
+    s->arena_bytes = (size_t)1 << top;
+    hipError_t e = hipMalloc(&s->arena, s->arena_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return set_error(BMMC_ERR_NOMEM, "server arena of %zu bytes: %s", (size_t)1 << top, hipGetErrorString(e));
+    }
+    s->buddy.init(top, 12);
+    s->slots.resize(s->opt.streams);
+    for (Slot& sl : s->slots) {
+        hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    }
+    s->planner = std::thread([s] { s->plan_loop(); });
+    s->dispatcher = std::thread([s] { s->dispatch_loop(); });
+    *handle_out = s;
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_submit(void* handle, const bmmc_desc_t* desc, int64_t arrival_ns, int64_t* ticket_out) {
+    Server* s = (Server*)handle;
+    if (!s || !desc || !ticket_out) return set_error(BMMC_ERR_ARG, "NULL argument");
+    const bmmc_desc_t& d = *desc;
+    if (d.n < 0 || d.n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n out of range");
+    if (!(d.elem_bytes == 1 || d.elem_bytes == 2 || d.elem_bytes == 4 || d.elem_bytes == 8 || d.elem_bytes == 16))
+        return set_error(BMMC_ERR_ARG, "bad elem_bytes");
+    if (d.n > 0 && !d.A_rows) return set_error(BMMC_ERR_ARG, "A_rows is NULL");
+    const size_t bytes = ((size_t)1 << d.n) * (size_t)d.elem_bytes;
+    if (!d.in || ((uintptr_t)d.in & 15u)) return set_error(BMMC_ERR_ARG, "in must be 16-byte aligned device memory");
+    if (!s->opt.own_outputs) {
+        int st = validate_buffers(d.in, d.out, bytes);
+        if (st != BMMC_OK) return st;
+    }
+    if ((int64_t)(3 * bytes) > s->opt.budget_bytes || bytes > s->arena_bytes / 2)
+        return set_error(BMMC_ERR_NOMEM, "request of %zu bytes can never fit the budget", bytes);
+    auto* r = new Request();
+    r->desc = d;
+    for (int i = 0; i < d.n; i++) r->rows[i] = d.A_rows[i];
+    r->desc.A_rows = r->rows;
+    r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+    r->bytes = bytes;
+    r->footprint = 0;  // set at admission
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    s->table[r->ticket] = r;
+    s->submitted++;
+    if (s->first_arrival < 0 || r->arrival_ns < s->first_arrival) s->first_arrival = r->arrival_ns;
+    s->future.push(r);
+    s->cv_work.notify_all();
+    *ticket_out = r->ticket;
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_poll(void* handle, int64_t ticket, int wait, int64_t* done_ns, void** out_ptr) {
+    Server* s = (Server*)handle;
+    if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->table.find(ticket);
+    if (it == s->table.end()) return set_error(BMMC_ERR_NOTFOUND, "unknown ticket %lld", (long long)ticket);
+    Request* r = it->second;
+    if (wait) s->cv_done.wait(lk, [&] { return r->state == kDone || r->state == kFailed; });
+    if (r->state == kFailed) return set_error(r->status, "request failed: %s", bmmc_strerror(r->status));
+    if (r->state != kDone) return BMMC_ERR_BUSY;
+    if (done_ns) *done_ns = r->done_ns;
+    if (out_ptr) *out_ptr = r->desc.out;
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_release(void* handle, int64_t ticket) {
+    Server* s = (Server*)handle;
+    if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->table.find(ticket);
+    if (it == s->table.end()) return set_error(BMMC_ERR_NOTFOUND, "unknown ticket %lld", (long long)ticket);
+    Request* r = it->second;
+    if (r->state != kDone && r->state != kFailed) return set_error(BMMC_ERR_BUSY, "request still running");
+    if (r->out_off >= 0) {
+        s->buddy.release(r->out_off);
+        r->out_off = -1;
+    }
+    s->in_use -= (int64_t)r->footprint;
+    r->footprint = 0;
+    s->table.erase(it);
+    delete r;
+    s->cv_work.notify_all();
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_drain(void* handle) {
+    Server* s = (Server*)handle;
+    if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] {
+        for (auto& kv : s->table)
+            if (kv.second->state != kDone && kv.second->state != kFailed) return false;
+        return true;
+    });
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_stats(void* handle, bmmc_server_stats_t* out) {
+    Server* s = (Server*)handle;
+    if (!s || !out) return set_error(BMMC_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->rejected = s->rejected;
+    out->batches = s->batches;
+    out->bytes_moved = s->bytes_moved;
+    out->busy_s = s->first_arrival >= 0 ? (double)(s->last_done - s->first_arrival) * 1e-9 : 0.0;
+    out->in_use_bytes = s->in_use;
+    out->peak_bytes = s->peak;
+    out->mean_batch = s->batches ? s->batch_reqs / (double)s->batches : 0.0;
+    std::vector<double> v = s->latencies_ms;
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            size_t k = (size_t)(p * (double)(v.size() - 1) + 0.5);
+            return v[std::min(k, v.size() - 1)];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_ms = sum / (double)v.size();
+        out->max_ms = v.back();
+    }
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_server_destroy(void* handle) {
+    Server* s = (Server*)handle;
+    if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    s->planner.join();
+    s->dispatcher.join();
+    for (Slot& sl : s->slots) {
+        hipStreamSynchronize(sl.stream);
+        hipStreamDestroy(sl.stream);
+        hipEventDestroy(sl.done);
+    }
+    hipFree(s->arena);
+    for (auto& kv : s->table) delete kv.second;
+    while (!s->future.empty()) s->future.pop();
+    delete s;
+    return BMMC_OK;
+}

@@ -1,0 +1,300 @@
+// Autotuner: times candidate tile shapes and launch parameters on the device
+// and caches the fastest, per (n, width, method) for single arrays and per
+// batch signature for batched launches.  The cache can be saved to and loaded
+// from a JSON-lines file; BMMC_TUNE_CACHE names a file loaded on first use.
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace bmmc {
+
+namespace {
+
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::tuple<int, int, int>, std::pair<bmmc_options_t, double>> plain;
+    std::map<uint64_t, std::pair<bmmc_batch_options_t, double>> batch;
+};
+
+TuneCache& cache() {
+    static TuneCache c;
+    return c;
+}
+
+int load_file(TuneCache& c, const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return 0;
+    char line[512];
+    int count = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        bmmc_options_t o;
+        std::memset(&o, 0, sizeof(o));
+        int n, w, method;
+        double ms;
+        if (std::sscanf(line,
+                        "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
+                        "\"iters\": %d, \"t\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %lf}",
+                        &n, &w, &method, &o.threads, &o.iters, &o.t, &o.grid, &o.swizzle, &ms) == 9) {
+            o.method = method;
+            c.plain[{n, w, method}] = {o, ms};
+            count++;
+            continue;
+        }
+        bmmc_batch_options_t b;
+        std::memset(&b, 0, sizeof(b));
+        uint64_t sig;
+        if (std::sscanf(line,
+                        "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
+                        "\"order\": %d, \"method\": %d, \"ms\": %lf}",
+                        &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &ms) == 6) {
+            c.batch[sig] = {b, ms};
+            count++;
+        }
+    }
+    std::fclose(f);
+    return count;
+}
+
+void ensure_loaded(TuneCache& c) {
+    if (c.loaded) return;
+    c.loaded = true;
+    const char* path = std::getenv("BMMC_TUNE_CACHE");
+    if (path && *path) load_file(c, path);
+}
+
+int save_file(TuneCache& c, const char* path) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_error(BMMC_ERR_ARG, "cannot write %s", path);
+    for (auto& kv : c.plain) {
+        const bmmc_options_t& o = kv.second.first;
+        std::fprintf(f,
+                     "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
+                     "\"iters\": %d, \"t\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %.6f}\n",
+                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), o.threads, o.iters,
+                     o.t, o.grid, o.swizzle, kv.second.second);
+    }
+    for (auto& kv : c.batch) {
+        const bmmc_batch_options_t& b = kv.second.first;
+        std::fprintf(f,
+                     "{\"kind\": \"batch\", \"sig\": \"%016" PRIx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
+                     "\"order\": %d, \"method\": %d, \"ms\": %.6f}\n",
+                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, kv.second.second);
+    }
+    std::fclose(f);
+    return BMMC_OK;
+}
+
+void autosave(TuneCache& c) {
+    const char* path = std::getenv("BMMC_TUNE_CACHE");
+    if (path && *path) save_file(c, path);
+}
+
+uint64_t next_rand(uint64_t* s) {
+    uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// A random invertible matrix (rows drawn until independent) for timing.
+void random_matrix(int n, uint64_t seed, uint64_t* rows, uint64_t* c) {
+    Basis b;
+    int k = 0;
+    while (k < n) {
+        uint64_t r = next_rand(&seed) & low_mask(n);
+        if (b.insert(r)) rows[k++] = r;
+    }
+    *c = next_rand(&seed) & low_mask(n);
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() {
+        hipEventCreate(&a);
+        hipEventCreate(&b);
+    }
+    ~Timer() {
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+bool tuned_options(int n, int w, int method, bmmc_options_t* out) {
+    TuneCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    ensure_loaded(c);
+    auto it = c.plain.find({n, w, method});
+    if (it == c.plain.end()) return false;
+    *out = it->second.first;
+    return true;
+}
+
+bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out) {
+    TuneCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    ensure_loaded(c);
+    auto it = c.batch.find(signature);
+    if (it == c.batch.end()) return false;
+    *out = it->second.first;
+    return true;
+}
+
+}  // namespace bmmc
+
+using namespace bmmc;
+
+extern "C" int bmmc_tune_save(const char* path) {
+    if (!path) return set_error(BMMC_ERR_ARG, "path is NULL");
+    TuneCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    ensure_loaded(c);
+    return save_file(c, path);
+}
+
+extern "C" int bmmc_tune_load(const char* path) {
+    if (!path) return set_error(BMMC_ERR_ARG, "path is NULL");
+    TuneCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.loaded = true;
+    return load_file(c, path);
+}
+
+// Time every tile shape available for this width, two run widths and three
+// grid sizes on a random permutation of 2^n elements; keep the fastest.
+extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, int reps,
+                             bmmc_options_t* best_out, double* best_ms) {
+    if (n < 1 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n out of range");
+    if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
+        return set_error(BMMC_ERR_ARG, "bad elem_bytes");
+    if (reps < 1) reps = 3;
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
+    void *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
+        if (in) hipFree(in);
+        (void)hipGetLastError();
+        return set_error(BMMC_ERR_NOMEM, "autotune buffers of %zu bytes", bytes);
+    }
+    hipMemsetAsync(in, 0x5a, bytes, stream);
+    uint64_t rows[64], c;
+    random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, rows, &c);
+
+    static const int kShapes[][2] = {{256, 2}, {256, 4}, {256, 8}, {256, 16}, {512, 2}, {512, 4},
+                                     {512, 8}, {1024, 2}, {1024, 4}, {256, 1}};
+    double best = 1e30;
+    bmmc_options_t bo;
+    std::memset(&bo, 0, sizeof(bo));
+    Timer tm;
+    for (auto& sh : kShapes) {
+        if (!tiled_kernel_available(elem_bytes, sh[0], sh[1])) continue;
+        KernelShape ks = default_shape(elem_bytes);
+        ks.nt = sh[0];
+        ks.iters = sh[1];
+        const int D = ks.D();
+        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters);
+        for (int t = D / 2; t >= D / 2 - 1 && t >= ks.lv(); t--) {
+            for (int g = 0; g < 3; g++) {
+                bmmc_options_t o;
+                std::memset(&o, 0, sizeof(o));
+                o.method = method;
+                o.t = t;
+                o.threads = ks.nt;
+                o.iters = ks.iters;
+                o.swizzle = 1;
+                o.grid = g == 0 ? 0 : ds->cu_count * occ * g;
+                st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                if (st != BMMC_OK) continue;  // shape does not fit this size
+                hipEventRecord(tm.a, stream);
+                for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                hipEventRecord(tm.b, stream);
+                hipEventSynchronize(tm.b);
+                float ms = 0;
+                hipEventElapsedTime(&ms, tm.a, tm.b);
+                const double per = ms / reps;
+                if (per < best) {
+                    best = per;
+                    bo = o;
+                }
+            }
+        }
+    }
+    hipStreamSynchronize(stream);
+    hipFree(in);
+    hipFree(out);
+    if (best >= 1e30) return set_error(BMMC_ERR_RANGE, "no tile shape fits n = %d, w = %d", n, elem_bytes);
+    {
+        TuneCache& tc = cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        ensure_loaded(tc);
+        tc.plain[{n, elem_bytes, method}] = {bo, best};
+        autosave(tc);
+    }
+    if (best_out) *best_out = bo;
+    if (best_ms) *best_ms = best;
+    return BMMC_OK;
+}
+
+// Time chunk size, queue order and persistent grid size on this batch; keep
+// the fastest for batches with the same signature.
+extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* stream_, int reps,
+                                     bmmc_batch_options_t* best_out, double* best_ms) {
+    int st = batch_validate(descs, count);
+    if (st != BMMC_OK) return st;
+    if (count == 0) return set_error(BMMC_ERR_ARG, "empty batch");
+    if (reps < 1) reps = 3;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    const int occ = batched_occupancy();
+    static const int kChunks[] = {1, 2, 4, 8, 16};
+    double best = 1e30;
+    bmmc_batch_options_t bo;
+    std::memset(&bo, 0, sizeof(bo));
+    Timer tm;
+    for (int chunk : kChunks) {
+        for (int order = 0; order < 3; order++) {
+            for (int g = 1; g <= 2; g++) {
+                bmmc_batch_options_t o;
+                std::memset(&o, 0, sizeof(o));
+                o.chunk_tiles = chunk;
+                o.order = order;
+                o.workgroups = ds->cu_count * occ * g / 2;
+                st = bmmc_permute_batched_ex(descs, count, &o, stream);  // warm-up
+                if (st != BMMC_OK) return st;
+                hipEventRecord(tm.a, stream);
+                for (int r = 0; r < reps; r++) bmmc_permute_batched_ex(descs, count, &o, stream);
+                hipEventRecord(tm.b, stream);
+                hipEventSynchronize(tm.b);
+                float ms = 0;
+                hipEventElapsedTime(&ms, tm.a, tm.b);
+                const double per = ms / reps;
+                if (per < best) {
+                    best = per;
+                    bo = o;
+                }
+            }
+        }
+    }
+    {
+        TuneCache& tc = cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        ensure_loaded(tc);
+        tc.batch[batch_signature(descs, count)] = {bo, best};
+        autosave(tc);
+    }
+    if (best_out) *best_out = bo;
+    if (best_ms) *best_ms = best;
+    return BMMC_OK;
+}

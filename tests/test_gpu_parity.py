@@ -1,0 +1,190 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI (GPU only).
+
+Every result is compared element by element, bit-exact (the output of a
+permutation is unique): full arrays at sizes the oracle handles quickly (that
+still span many tiles, plus sizes below one tile and below one wave), and the
+full-size workloads of the benchmark either in full or on sampled outputs that
+the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2306_07795_amd import binding as B
+from synth import gen
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def run(n, rows, c, w, a, fn="permute", opts=None):
+    x = G.to_device(a)
+    y = G.empty_like_bytes(a)
+    if fn == "permute":
+        B.bmmc_permute(x, y, n, rows, c, w, G.stream())
+    elif fn == "ex":
+        B.bmmc_permute_ex(x, y, n, rows, c, w, opts, G.stream())
+    elif fn == "naive":
+        B.bmmc_permute_naive(x, y, n, rows, c, w, G.stream())
+    G.sync()
+    return G.to_host(y, a)
+
+
+def check(n, rows, c, w, fn="permute", opts=None, seed=1):
+    a = gen.data(n, w, seed)
+    got = run(n, rows, c, w, a, fn, opts)
+    want = O.permute(a, n, rows, c)
+    assert np.array_equal(got, want), f"n={n} w={w} fn={fn} opts={opts}"
+
+
+def test_device_present():
+    assert torch.cuda.is_available()
+    print("device:", torch.cuda.get_device_name(0), flush=True)
+
+
+def test_bit_reversal_2p20_int32_full():
+    """Bit reversal of 2^20 int32 filled from seed 0 (one tiled pass)."""
+    n = 20
+    rows = gen.bit_reversal_rows(n)
+    p = B.bmmc_factorize(rows, 0, n)
+    assert p.nfactors == 1
+    a = gen.data(n, 4, 0)
+    assert np.array_equal(run(n, rows, 0, 4, a), O.permute(a, n, rows, 0))
+
+
+def test_random_2p26_int32_full():
+    """Random BMMC on 2^26 int32, seed 0: two tiled passes, full comparison."""
+    n = 26
+    rows, c = gen.random_bmmc(n, 0)
+    assert B.bmmc_factorize(rows, c, n).nfactors == 2
+    a = gen.data(n, 4, 0)
+    got = run(n, rows, c, 4, a)
+    assert np.array_equal(got, O.permute(a, n, rows, c))
+
+
+@pytest.mark.parametrize("w", [4, 8])
+@pytest.mark.parametrize("kind", ["random", "bitrev", "swap", "bpc", "cyclic", "reverse", "identity"])
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 9, 12, 13, 15, 18])
+def test_small_sizes(kind, n, w):
+    s = 31 * n + w
+    rows, c = {
+        "random": lambda: gen.random_bmmc(n, s),
+        "bitrev": lambda: (gen.bit_reversal_rows(n), 0),
+        "swap": lambda: (gen.block_swap_rows(n, n // 2), 0),
+        "bpc": lambda: gen.random_bpc(n, s),
+        "cyclic": lambda: (gen.cyclic_shift_rows(n), 1),
+        "reverse": lambda: (gen.identity_rows(n), (1 << n) - 1),
+        "identity": lambda: (gen.identity_rows(n), 0),
+    }[kind]()
+    check(n, rows, c, w)
+
+
+@pytest.mark.parametrize("w", [1, 2, 16])
+@pytest.mark.parametrize("n", [0, 1, 3, 5, 8, 11, 14, 17])
+def test_other_widths(n, w):
+    rows, c = gen.random_bmmc(n, 7 + n)
+    check(n, rows, c, w)
+
+
+@pytest.mark.parametrize("w", [4, 8, 16])
+@pytest.mark.parametrize("n", [0, 5, 12, 16, 19])
+def test_naive_kernel(n, w):
+    rows, c = gen.random_bmmc(n, 3 * n)
+    check(n, rows, c, w, fn="naive")
+
+
+@pytest.mark.parametrize("n", [10, 14, 17, 20])
+@pytest.mark.parametrize("w", [4, 8])
+def test_onepass_method(n, w):
+    rows, c = gen.random_bmmc(n, 11 * n)
+    check(n, rows, c, w, fn="ex", opts={"method": B.METHOD_ONEPASS})
+
+
+@pytest.mark.parametrize("opts", [
+    {"threads": 512, "iters": 4}, {"threads": 1024, "iters": 2}, {"threads": 256, "iters": 8},
+    {"threads": 256, "iters": 2}, {"threads": 1024, "iters": 4}, {"t": 5},
+    {"swizzle": -1}, {"grid": 64}, {"grid": 1}, {"threads": 256, "iters": 16, "t": 7},
+])
+def test_shapes_and_grids(opts):
+    n = 19
+    rows, c = gen.random_bmmc(n, 99)
+    check(n, rows, c, 4, fn="ex", opts=opts)
+
+
+@pytest.mark.parametrize("opts", [{"threads": 256, "iters": 4}, {"threads": 512, "iters": 8},
+                                  {"threads": 256, "iters": 16, "t": 7}])
+def test_shapes_int64(opts):
+    n = 18
+    rows, c = gen.random_bmmc(n, 98)
+    check(n, rows, c, 8, fn="ex", opts=opts)
+
+
+def test_iota_payload_names_sources():
+    n = 22
+    rows, c = gen.random_bmmc(n, 5)
+    a = gen.iota(n, 4)
+    got = run(n, rows, c, 4, a)
+    ys = O.index_map(rows, c, n).astype(np.int64)
+    assert np.array_equal(got[ys], a)
+
+
+def sampled_check(n, rows, c, w, got, a, count=1 << 16, seed=0):
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, 1 << n, size=count, dtype=np.uint64)
+    xs[:4] = [0, 1, (1 << n) - 2, (1 << n) - 1]
+    ys = O.apply_many(rows, c, n, xs).astype(np.int64)
+    assert np.array_equal(got[ys], a[xs.astype(np.int64)])
+
+
+@pytest.mark.parametrize("case", ["random28_i32", "random27_i64", "bitrev28_i32", "swap28_i32",
+                                  "swap27_i64"])
+def test_full_size_sweep_sampled(case):
+    """The 1 GiB sweep arrays in the benchmark's launch configuration, checked
+    on 65536 sampled outputs computed one by one by the oracle."""
+    n, w = (28, 4) if case.endswith("i32") else (27, 8)
+    if case.startswith("random"):
+        rows, c = gen.random_bmmc(n, 1)
+    elif case.startswith("bitrev"):
+        rows, c = gen.bit_reversal_rows(n), 0
+    else:
+        rows, c = gen.block_swap_rows(n, n // 2), 0
+    a = gen.data(n, w, 1)
+    got = run(n, rows, c, w, a)
+    sampled_check(n, rows, c, w, got, a)
+
+
+def test_copy_kernel():
+    for nbytes in (16, 4096, 1 << 22, (1 << 20) + 5, 3):
+        a = np.frombuffer(np.random.default_rng(nbytes).bytes(nbytes), dtype=np.uint8).copy()
+        x = G.to_device(a)
+        y = torch.zeros(nbytes, dtype=torch.uint8, device=G.dev())
+        B.bmmc_copy(x, y, nbytes, G.stream())
+        G.sync()
+        assert np.array_equal(y.cpu().numpy(), a)
+
+
+def test_same_result_on_side_stream():
+    n = 20
+    rows, c = gen.random_bmmc(n, 77)
+    a = gen.data(n, 4, 2)
+    x = G.to_device(a)
+    y = G.empty_like_bytes(a)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.bmmc_permute(x, y, n, rows, c, 4, s)
+    s.synchronize()
+    assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
+
+
+def test_profile_reports_launches():
+    n = 20
+    rows, c = gen.random_bmmc(n, 9)
+    a = gen.data(n, 4, 2)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    B.bmmc_profile_begin()
+    for _ in range(3):
+        B.bmmc_permute(x, y, n, rows, c, 4, G.stream())
+    st = B.bmmc_profile_end()
+    assert sum(v["launches"] for v in st.values()) == 6
+    assert all(v["total_ms"] > 0 for v in st.values())

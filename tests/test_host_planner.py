@@ -1,0 +1,336 @@
+"""Host logic of the GPU library, checked on the CPU (no device calls).
+
+The library's planner and its host emulation of the kernels' addressing are
+compared with the oracle (which shares no code with them): factor products,
+the tiled condition, the paper's geometry examples, and full permutations run
+lane by lane on the host.
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2306_07795_amd import binding as B
+from synth import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "bmmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bmmc_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 25
+    L = B.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(B.exported_names())
+    assert B.bmmc_version() >= 100
+
+
+def test_strerror_and_errors():
+    assert B.bmmc_strerror(0) == "ok"
+    assert "singular" in B.bmmc_strerror(-2)
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_factorize([0b011, 0b110, 0b101], 0, 3)
+    assert e.value.status == -2
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_factorize([1, 2, 1 << 5], 0, 3)  # bit beyond n
+    assert e.value.status == -1
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_factorize(gen.identity_rows(3), 8, 3)  # complement bit beyond n
+    assert e.value.status == -1
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_factorize(gen.identity_rows(33), 0, 33)
+    assert e.value.status == -3
+    with pytest.raises(B.BmmcError):
+        B.bmmc_plan_ex(gen.identity_rows(4), 0, 4, 3)  # width 3
+    # buffer validation happens before any device call
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_permute(0, 0, 4, gen.identity_rows(4), 0, 4)
+    assert e.value.status == -1
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_permute(4096, 4096 + 32, 4, gen.identity_rows(4), 0, 4)  # overlap
+    assert e.value.status == -4
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_permute(4096 + 4, 1 << 20, 4, gen.identity_rows(4), 0, 4)  # misaligned
+    assert e.value.status == -1
+
+
+def test_batched_validation_rejects_overlaps():
+    rows = gen.identity_rows(4)
+    base = 1 << 20
+    ok = [(base, base + 4096, 4, 4, rows, 0), (base + 8192, base + 12288, 4, 4, rows, 0)]
+    shared_input = [(base, base + 4096, 4, 4, rows, 0), (base, base + 8192, 4, 4, rows, 0)]
+    clash = [(base, base + 4096, 4, 4, rows, 0), (base + 8192, base + 4096 + 16, 4, 4, rows, 0)]
+    in_on_out = [(base, base + 4096, 4, 4, rows, 0), (base + 4096 + 32, base + 8192, 4, 4, rows, 0)]
+    arr, keep, k = B.make_descs(clash)
+    assert B.lib().bmmc_permute_batched(arr, k, None) == -4
+    arr, keep, k = B.make_descs(in_on_out)
+    assert B.lib().bmmc_permute_batched(arr, k, None) == -4
+    # valid batches get past validation and then need a device (HIP error here)
+    for items in (ok, shared_input):
+        arr, keep, k = B.make_descs(items)
+        assert B.lib().bmmc_permute_batched(arr, k, None) in (0, -6)
+
+
+# ---------------------------------------------------------- tiled test
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (8, 1), (12, 2), (20, 3), (28, 4)])
+def test_is_tiled_matches_oracle_definition(n, seed):
+    mats = [gen.random_bmmc(n, seed)[0], gen.bit_reversal_rows(n), gen.block_swap_rows(n, n // 2),
+            gen.random_bpc(n, seed)[0], gen.cyclic_shift_rows(n)]
+    for rows in mats:
+        m = O.dense(rows, n)
+        for t in range(0, n + 1):
+            ok, cols = O.is_tiled(m, t)
+            got, mask = B.bmmc_is_tiled(rows, n, t)
+            assert got == ok
+            if ok:
+                assert mask == cols
+
+
+# ------------------------------------------------------- factorization
+
+def check_ulp(rows, n):
+    f = B.bmmc_factorize_ulp(rows, n)
+    U, L, P = (O.dense(f[k], n) for k in ("U", "L", "P"))
+    T1, T2 = O.dense(f["T1"], n), O.dense(f["T2"], n)
+    A = O.dense(rows, n)
+    R = O.dense(gen.bit_reversal_rows(n), n)
+    assert np.array_equal(np.triu(U), U) and np.all(np.diag(U) == 1)
+    assert np.array_equal(np.tril(L), L) and np.all(np.diag(L) == 1)
+    assert np.all(P.sum(0) == 1) and np.all(P.sum(1) == 1)
+    assert np.array_equal(O.mul(O.mul(U, L), P), A)
+    assert np.array_equal(O.mul(U, R), T1)
+    assert np.array_equal(O.mul(R, O.mul(L, P)), T2)
+    assert np.array_equal(O.mul(T1, T2), A)
+    for t in range(n + 1):
+        ok1, cols1 = O.is_tiled(T1, t)
+        ok2, _ = O.is_tiled(T2, t)
+        assert ok1 and ok2
+        assert cols1 == sum(1 << j for j in range(n - t, n))  # U.R on the top columns
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_ulp_brute_force_every_invertible_matrix(n):
+    import itertools
+    count = 0
+    for rows in itertools.product(range(1 << n), repeat=n):
+        if O.rank(O.dense(rows, n)) != n:
+            continue
+        count += 1
+        check_ulp(list(rows), n)
+    assert count == {1: 1, 2: 6, 3: 168}[n]
+
+
+def test_ulp_n4_sample_of_all():
+    import itertools
+    seen = 0
+    for k, rows in enumerate(itertools.product(range(16), repeat=4)):
+        if k % 7:
+            continue
+        if O.rank(O.dense(rows, 4)) != 4:
+            continue
+        check_ulp(list(rows), 4)
+        seen += 1
+    assert seen > 2500
+
+
+@pytest.mark.parametrize("n,seed", [(12, 1), (17, 2), (22, 3), (26, 4), (28, 5), (32, 6)])
+def test_ulp_random(n, seed):
+    check_ulp(gen.random_bmmc(n, seed)[0], n)
+
+
+@pytest.mark.parametrize("n,seed,w", [(14, 1, 4), (20, 2, 4), (26, 0, 4), (28, 3, 4), (27, 4, 8), (24, 5, 16)])
+def test_plan_factors(n, seed, w):
+    """Planned factors compose to A, complement on the second, each tiled at t."""
+    rows, c = gen.random_bmmc(n, seed)
+    p = B.bmmc_factorize_t(rows, c, n, 0, w)
+    assert p.nfactors == 2
+    t = p.t
+    (r0, c0), (r1, c1) = p.factor(0), p.factor(1)
+    assert c0 == 0 and c1 == c
+    T2, T1 = O.dense(r0, n), O.dense(r1, n)
+    assert np.array_equal(O.mul(T1, T2), O.dense(rows, n))
+    assert O.is_tiled(T1, t)[0] and O.is_tiled(T2, t)[0]
+    for k in range(2):
+        assert p.coordinate[k] == 1
+        assert p.lds_conflict_score[k] == 0
+        assert p.tile_bits[k] == {4: 12, 8: 12, 16: 11}[w]
+
+
+def test_tiled_matrix_takes_one_pass():
+    n = 20
+    for rows in (gen.bit_reversal_rows(n), gen.block_swap_rows(n, 10), gen.random_bpc(n, 3)[0]):
+        p = B.bmmc_factorize(rows, 5, n)
+        assert p.nfactors == 1
+        assert p.factor(0) == (rows, 5)
+
+
+# ----------------------------------------------- geometry pins (paper values)
+
+def pdep(value, mask):
+    out, k = 0, 0
+    for j in range(64):
+        if (mask >> j) & 1:
+            out |= ((value >> k) & 1) << j
+            k += 1
+    return out
+
+
+def compress(index, mask):
+    """Delete the bits of index outside mask (the stitch_tile_* view)."""
+    out, k = 0, 0
+    for j in range(64):
+        if (mask >> j) & 1:
+            out |= ((index >> j) & 1) << k
+            k += 1
+    return out
+
+
+def test_stitch_examples_cyclic_shift():
+    g = GOLDEN["stitch_cyclic_shift"]
+    n, t = g["n"], g["t"]
+    rows = gen.cyclic_shift_rows(n)
+    # tile of exactly the paper's bits: 2t - n_over = 6 bits, no iterations
+    p = B.bmmc_plan_ex(rows, 0, n, 16, {"t": t, "threads": 64, "iters": 1})
+    assert p.nfactors == 1
+    col, row, tb = p.col_mask[0], p.tile_rows_mask[0], p.tb_mask[0]
+    assert p.n_over[0] == g["n_over"] and bin(tb).count("1") == g["n_tb"] and p.iter_mask[0] == 0
+    assert col == (1 << t) - 1
+    tile = col | row
+
+    def stitch_col(c_, tb_, r_):
+        return pdep(c_, col) | pdep(tb_, tb) | pdep(r_, row & ~col)
+
+    def stitch_row(c_, tb_, r_):
+        return pdep(r_, row) | pdep(tb_, tb) | pdep(c_, col & ~row)
+
+    for ex in g["examples"]:
+        b = lambda s: int(s, 2)
+        if ex["fn"] == "stitch_col":
+            got = stitch_col(b(ex["col"]), b(ex["tb"]), b(ex["row"]))
+        elif ex["fn"] == "stitch_row":
+            got = stitch_row(b(ex["col"]), b(ex["tb"]), b(ex["row"]))
+        elif ex["fn"] == "stitch_tile_col":
+            got = compress(stitch_col(b(ex["col"]), 0, b(ex["row"])), tile)
+        else:
+            got = compress(stitch_row(b(ex["col"]), 0, b(ex["row"])), tile)
+        assert got == b(ex["result"]), ex
+
+
+def test_appendix_geometry_bit_reverse():
+    g = GOLDEN["appendix_bitrev15"]
+    n, t = g["n"], g["t"]
+    rows = gen.bit_reversal_rows(n)
+    bits = lambda m: [j for j in range(n) if (m >> j) & 1]
+    # tile of 2^10 = 1024 elements (no iteration bits)
+    p = B.bmmc_plan_ex(rows, 0, n, 16, {"t": t, "threads": 1024, "iters": 1})
+    assert bits(p.col_mask[0]) == g["col_bits"]
+    assert bits(p.tile_rows_mask[0]) == g["row_bits"]
+    assert bits(p.tb_mask[0]) == g["tb_bits"]
+    assert p.n_over[0] == g["n_over"]
+    assert 2 ** bin(p.tb_mask[0]).count("1") == g["blocks"]
+    assert 2 ** p.tile_bits[0] == g["tile_elems"]
+    # n_iter = 3: tile of 2^13 = 8192 elements
+    it = g["iters"]
+    p = B.bmmc_plan_ex(rows, 0, n, 16, {"t": t, "threads": 1024, "iters": 8})
+    assert bits(p.iter_mask[0]) == it["iter_bits"]
+    assert bits(p.tb_mask[0]) == it["tb_bits"]
+    assert 2 ** bin(p.tb_mask[0]).count("1") == it["blocks"]
+    assert 2 ** p.tile_bits[0] == it["tile_elems"]
+
+
+# ------------------------------------------- host emulation vs the oracle
+
+def emulate_check(n, rows, c, w, opts=None, data_seed=1):
+    a = gen.data(n, w, data_seed)
+    out = np.zeros_like(a)
+    st = B.bmmc_emulate(a, out, n, rows, c, w, opts)
+    assert np.array_equal(out, O.permute(a, n, rows, c))
+    assert st["lds_slot_errors"] == 0
+    return st
+
+
+CASES = [
+    ("random", lambda n, s: gen.random_bmmc(n, s)),
+    ("bitrev", lambda n, s: (gen.bit_reversal_rows(n), 0)),
+    ("swap", lambda n, s: (gen.block_swap_rows(n, n // 2), 0)),
+    ("bpc", lambda n, s: gen.random_bpc(n, s)),
+    ("cyclic", lambda n, s: (gen.cyclic_shift_rows(n), 1)),
+    ("reverse", lambda n, s: (gen.identity_rows(n), (1 << n) - 1)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("n", [3, 8, 12, 13, 16, 18])
+@pytest.mark.parametrize("w", [4, 8])
+def test_emulation_matches_oracle(name, mk, n, w):
+    rows, c = mk(n, n * 13 + w)
+    st = emulate_check(n, rows, c, w)
+    if n >= 8:
+        # every wave access is one run of whole lines, and conflict-free LDS
+        assert st["read_lines"] == st["read_lines_min"]
+        assert st["write_lines"] == st["write_lines_min"]
+        assert st["lds_conflicts32"] == 0 and st["lds_conflicts64"] == 0
+
+
+@pytest.mark.parametrize("w", [1, 2, 16])
+@pytest.mark.parametrize("n", [2, 5, 11, 15, 17])
+def test_emulation_other_widths(w, n):
+    rows, c = gen.random_bmmc(n, 100 + n)
+    emulate_check(n, rows, c, w)
+
+
+@pytest.mark.parametrize("method", [B.METHOD_ONEPASS, B.METHOD_NAIVE])
+@pytest.mark.parametrize("n", [9, 14, 17])
+def test_emulation_methods(method, n):
+    rows, c = gen.random_bmmc(n, 7 * n)
+    st = emulate_check(n, rows, c, 4, {"method": method})
+    if method == B.METHOD_ONEPASS and n >= 13:
+        assert st["tiles"] == 2 ** (n - 12)  # one pass over all tiles
+        assert st["read_lines"] == st["read_lines_min"]
+        assert st["lds_conflicts64"] == 0
+
+
+@pytest.mark.parametrize("opts", [
+    {"threads": 512, "iters": 4}, {"threads": 1024, "iters": 2}, {"threads": 256, "iters": 8},
+    {"threads": 256, "iters": 2}, {"t": 5}, {"t": 4, "threads": 256, "iters": 2},
+    {"swizzle": -1}, {"threads": 256, "iters": 16, "t": 7},
+])
+def test_emulation_shapes(opts):
+    n = 17
+    rows, c = gen.random_bmmc(n, 5)
+    st = emulate_check(n, rows, c, 4, opts)
+    if opts.get("swizzle", 0) >= 0:
+        assert st["lds_conflicts64"] == 0
+
+
+def test_emulation_iota_two_pass_n20():
+    n = 20
+    rows, c = gen.random_bmmc(n, 20)
+    a = gen.iota(n, 4)
+    out = np.zeros_like(a)
+    B.bmmc_emulate(a, out, n, rows, c, 4)
+    ys = O.index_map(rows, c, n)
+    assert np.array_equal(out[ys.astype(np.int64)], a)
+
+
+def test_plain_layout_has_conflicts_that_the_swizzle_removes():
+    n = 16
+    rows = gen.bit_reversal_rows(n)
+    a = gen.data(n, 4, 0)
+    out = np.zeros_like(a)
+    plain = B.bmmc_emulate(a, out, n, rows, 0, 4, {"swizzle": -1})
+    swz = B.bmmc_emulate(a, out, n, rows, 0, 4)
+    assert plain["lds_conflicts32"] > 0
+    assert swz["lds_conflicts32"] == 0 and swz["lds_conflicts64"] == 0
