@@ -113,7 +113,7 @@ def test_shapes_and_grids(opts):
 
 
 @pytest.mark.parametrize("opts", [{"threads": 256, "iters": 4}, {"threads": 512, "iters": 8},
-                                  {"threads": 256, "iters": 16, "t": 7}])
+                                  {"threads": 256, "iters": 16, "t": 6}])
 def test_shapes_int64(opts):
     n = 18
     rows, c = gen.random_bmmc(n, 98)
