@@ -80,6 +80,13 @@ typedef struct {
     int iters;     /* 16-byte vectors per thread per tile */
     int swizzle;   /* 1 (default) conflict-avoiding LDS layout, -1 plain layout */
     int grid;      /* work-groups per pass launch; 0 = one per tile */
+    int run_in;    /* read-run bits (input runs of 2^run_in elements); 0 = t */
+    int run_out;   /* write-run bits (output runs of 2^run_out elements); 0 = t */
+    int hints;     /* bit 0: non-temporal loads, bit 1: non-temporal stores */
+    /* bit 0: give each XCD a contiguous range of tiles (work-groups are
+       dealt to the 8 XCDs round-robin); bit 1: select tiles through mixed
+       (XOR-combined) index bits instead of plain index bits. */
+    int tile_order;
     int reserved[2];
 } bmmc_options_t;
 
@@ -207,6 +214,9 @@ int bmmc_permute_naive(const void* in, void* out, int n, const uint64_t* A_rows,
 /* Upper bound (Section 2.3 "copy"): out[i] = in[i] for `bytes` bytes with
    16-byte vector loads and stores.  Pointers must not overlap. */
 int bmmc_copy(const void* in, void* out, size_t bytes, void* stream);
+/* The same copy with a chosen kernel: vpt 16-byte vectors per lane (1, 2, 4
+   or 8), hints as in bmmc_options_t.  bmmc_copy uses vpt = 4, hints = 0. */
+int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, void* stream);
 
 /* Many independent permutations, each with its own n, width, A and c, in one
    persistent kernel launch replayed from a captured hipGraph.  Arrays that fit

@@ -30,7 +30,8 @@ class BmmcError(RuntimeError):
 
 class Options(_c.Structure):
     _fields_ = [("method", _i32), ("t", _i32), ("threads", _i32), ("iters", _i32),
-                ("swizzle", _i32), ("grid", _i32), ("reserved", _i32 * 2)]
+                ("swizzle", _i32), ("grid", _i32), ("run_in", _i32), ("run_out", _i32),
+                ("hints", _i32), ("tile_order", _i32), ("reserved", _i32 * 2)]
 
 
 class Plan(_c.Structure):
@@ -106,6 +107,7 @@ def lib():
         "bmmc_permute_ex": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, P(Options), _vp]),
         "bmmc_permute_naive": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
         "bmmc_copy": (_i32, [_vp, _vp, _c.c_size_t, _vp]),
+        "bmmc_copy_ex": (_i32, [_vp, _vp, _c.c_size_t, _i32, _i32, _vp]),
         "bmmc_permute_batched": (_i32, [P(Desc), _i32, _vp]),
         "bmmc_permute_batched_ex": (_i32, [P(Desc), _i32, P(BatchOptions), _vp]),
         "bmmc_batched_status": (_i32, [_vp, P(_i32)]),
@@ -136,7 +138,7 @@ def exported_names():
     return [
         "bmmc_strerror", "bmmc_last_error", "bmmc_version", "bmmc_is_tiled", "bmmc_factorize",
         "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
-        "bmmc_copy", "bmmc_permute_batched", "bmmc_permute_batched_ex", "bmmc_batched_status",
+        "bmmc_copy", "bmmc_copy_ex", "bmmc_permute_batched", "bmmc_permute_batched_ex", "bmmc_batched_status",
         "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
@@ -260,6 +262,10 @@ def bmmc_permute_naive(inp, out, n: int, A_rows, c: int, elem_bytes: int, stream
 
 def bmmc_copy(inp, out, nbytes: int, stream=None):
     _check(lib().bmmc_copy(_ptr(inp), _ptr(out), nbytes, _stream(stream)))
+
+
+def bmmc_copy_ex(inp, out, nbytes: int, vpt: int = 4, hints: int = 0, stream=None):
+    _check(lib().bmmc_copy_ex(_ptr(inp), _ptr(out), nbytes, vpt, hints, _stream(stream)))
 
 
 def make_descs(items):

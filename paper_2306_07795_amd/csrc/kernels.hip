@@ -29,6 +29,19 @@ union Vec16 {
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
+// 16-byte global accesses; HINT bit 0 marks loads and bit 1 stores as
+// non-temporal (streamed, not kept in the caches).
+template <int HINT>
+__device__ __forceinline__ u32x4 ld16(const u32x4* p) {
+    if constexpr (HINT & 1) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <int HINT>
+__device__ __forceinline__ void st16(u32x4* p, u32x4 v) {
+    if constexpr (HINT & 2) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // XOR of tab[BASE + k] over the set bits k of a compile-time value.
 template <int BASE, int NBITS>
 __device__ __forceinline__ uint32_t lin_const(const uint32_t* tab, uint32_t v) {
@@ -52,7 +65,7 @@ __device__ __forceinline__ uint32_t lin_const(const uint32_t* tab, uint32_t v) {
 //   s = it * NT * VEC + tid * VEC + e.
 // Slots at or above 2^d do not exist when the array is smaller than the tile.
 // ---------------------------------------------------------------------------
-template <int W, int NT, int ITERS>
+template <int W, int NT, int ITERS, int HINT = 0>
 struct TileCtx {
     using E = typename ElemT<W>::T;
     static constexpr int VEC = 16 / W;
@@ -95,7 +108,7 @@ struct TileCtx {
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
                 const uint32_t x = r ^ xt ^ lin_const<LV + LT, LI>(P.X, it);
-                buf[it].v = in[x >> LV];
+                buf[it].v = ld16<HINT>(in + (x >> LV));
             }
         }
 #pragma unroll
@@ -115,58 +128,78 @@ struct TileCtx {
 #pragma unroll
                 for (int e = 0; e < VEC; e++) o.e[e] = lds[g ^ lin_const<0, LV>(P.G, e)];
                 const uint32_t y = yb ^ yt ^ lin_const<LV + LT, LI>(P.Y, it);
-                out[y >> LV] = o.v;
+                st16<HINT>(out + (y >> LV), o.v);
             }
         }
         __syncthreads();
     }
 };
 
-template <int W, int NT, int ITERS>
+// Work-groups are dealt to the XCDs round-robin (block b runs on XCD
+// b mod xcds).  With xcds > 0, renumber them so that each XCD owns one
+// contiguous range of logical blocks, hence of tiles: the work-groups sharing
+// an XCD's L2 then cover every value of the low tile bits.
+__device__ __forceinline__ uint32_t logical_block(uint32_t xcds) {
+    const uint32_t b = blockIdx.x;
+    if (xcds <= 1) return b;
+    const uint32_t g = gridDim.x, per = g / xcds, rem = g % xcds;
+    const uint32_t x = b % xcds, k = b / xcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+template <int W, int NT, int ITERS, int HINT>
 __global__ void __launch_bounds__(NT)
-k_tiled(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, uint32_t ntiles) {
-    using C = TileCtx<W, NT, ITERS>;
+k_tiled(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, uint32_t ntiles,
+        uint32_t xcds) {
+    using C = TileCtx<W, NT, ITERS, HINT>;
     __shared__ typename C::E lds[1 << C::D];
     C ctx;
     ctx.init(P, threadIdx.x);
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    for (uint32_t tile = logical_block(xcds); tile < ntiles; tile += gridDim.x)
         ctx.run(P, in, out, lds, tile, threadIdx.x);
 }
 
 struct TiledEntry {
-    int w, nt, iters;
-    void (*fn)(const u32x4*, u32x4*, const PassTables, uint32_t);
+    int w, nt, iters, hints;
+    void (*fn)(const u32x4*, u32x4*, const PassTables, uint32_t, uint32_t);
 };
 
-#define BMMC_TILED(W, NT, IT) {W, NT, IT, k_tiled<W, NT, IT>}
+#define BMMC_TILED(W, NT, IT) {W, NT, IT, 0, k_tiled<W, NT, IT, 0>}
+#define BMMC_TILED_H(W, NT, IT)                                                      \
+    {W, NT, IT, 0, k_tiled<W, NT, IT, 0>}, {W, NT, IT, 1, k_tiled<W, NT, IT, 1>},    \
+        {W, NT, IT, 2, k_tiled<W, NT, IT, 2>}, {W, NT, IT, 3, k_tiled<W, NT, IT, 3>}
 static const TiledEntry kTiled[] = {
-    BMMC_TILED(4, 256, 4),  BMMC_TILED(4, 256, 8),  BMMC_TILED(4, 256, 2), BMMC_TILED(4, 512, 4),
-    BMMC_TILED(4, 512, 2),  BMMC_TILED(4, 1024, 2), BMMC_TILED(4, 1024, 4), BMMC_TILED(4, 256, 16),
-    BMMC_TILED(8, 256, 8),  BMMC_TILED(8, 256, 4),  BMMC_TILED(8, 512, 4), BMMC_TILED(8, 512, 8),
-    BMMC_TILED(8, 1024, 4), BMMC_TILED(8, 256, 16),
-    BMMC_TILED(16, 256, 8), BMMC_TILED(16, 256, 4), BMMC_TILED(16, 512, 4),
-    BMMC_TILED(2, 256, 2),  BMMC_TILED(2, 256, 4),
-    BMMC_TILED(1, 256, 1),  BMMC_TILED(1, 256, 4),
+    BMMC_TILED_H(4, 256, 4),  BMMC_TILED_H(4, 512, 4),  BMMC_TILED_H(4, 256, 8), BMMC_TILED_H(4, 512, 2),
+    BMMC_TILED(4, 256, 2),    BMMC_TILED(4, 1024, 2),   BMMC_TILED(4, 1024, 4),  BMMC_TILED(4, 256, 16),
+    BMMC_TILED(4, 512, 8),
+    BMMC_TILED_H(8, 256, 4),  BMMC_TILED_H(8, 512, 4),  BMMC_TILED_H(8, 256, 8), BMMC_TILED(8, 512, 8),
+    BMMC_TILED(8, 1024, 4),   BMMC_TILED(8, 256, 16),   BMMC_TILED(8, 256, 2),   BMMC_TILED(8, 512, 2),
+    BMMC_TILED_H(16, 256, 4), BMMC_TILED_H(16, 256, 8), BMMC_TILED(16, 512, 4),  BMMC_TILED(16, 256, 2),
+    BMMC_TILED(2, 256, 2),    BMMC_TILED(2, 256, 4),
+    BMMC_TILED(1, 256, 1),    BMMC_TILED(1, 256, 4),
 };
 #undef BMMC_TILED
+#undef BMMC_TILED_H
 
-bool tiled_kernel_available(int w, int nt, int iters) {
+static const TiledEntry* find_tiled(int w, int nt, int iters, int hints) {
     for (const auto& e : kTiled)
-        if (e.w == w && e.nt == nt && e.iters == iters) return true;
-    return false;
+        if (e.w == w && e.nt == nt && e.iters == iters && e.hints == hints) return &e;
+    return nullptr;
 }
 
-hipError_t launch_tiled(int w, int nt, int iters, const void* in, void* out, const PassTables& tab,
-                        uint32_t ntiles, uint32_t grid, hipStream_t stream) {
-    for (const auto& e : kTiled) {
-        if (e.w == w && e.nt == nt && e.iters == iters) {
-            if (grid == 0 || grid > ntiles) grid = ntiles;
-            hipLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out,
-                               tab, ntiles);
-            return hipGetLastError();
-        }
-    }
-    return hipErrorInvalidValue;
+bool tiled_kernel_available(int w, int nt, int iters, int hints) {
+    return find_tiled(w, nt, iters, hints) != nullptr;
+}
+
+hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, void* out,
+                        const PassTables& tab, uint32_t ntiles, uint32_t grid, uint32_t xcds,
+                        hipStream_t stream) {
+    const TiledEntry* e = find_tiled(w, nt, iters, hints);
+    if (!e) return hipErrorInvalidValue;
+    if (grid == 0 || grid > ntiles) grid = ntiles;
+    hipLaunchKernelGGL(e->fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab,
+                       ntiles, xcds);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -234,18 +267,19 @@ hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs
 }
 
 // ---------------------------------------------------------------------------
-// Copy: 4 independent 16-byte vectors per lane (Section 2.3 "copy" bound).
+// Copy: VPT independent 16-byte vectors per lane (Section 2.3 "copy" bound).
 // ---------------------------------------------------------------------------
+template <int VPT, int HINT>
 __global__ void __launch_bounds__(256)
 k_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, uint64_t nvec) {
-    const uint64_t base = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
-    u32x4 v[4];
+    const uint64_t base = (uint64_t)blockIdx.x * (256 * VPT) + threadIdx.x;
+    u32x4 v[VPT];
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-        if (base + k * 256 < nvec) v[k] = in[base + k * 256];
+    for (int k = 0; k < VPT; k++)
+        if (base + k * 256 < nvec) v[k] = ld16<HINT>(in + base + k * 256);
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-        if (base + k * 256 < nvec) out[base + k * 256] = v[k];
+    for (int k = 0; k < VPT; k++)
+        if (base + k * 256 < nvec) st16<HINT>(out + base + k * 256, v[k]);
 }
 
 __global__ void k_copy_tail(const uint8_t* in, uint8_t* out, uint32_t count) {
@@ -253,12 +287,30 @@ __global__ void k_copy_tail(const uint8_t* in, uint8_t* out, uint32_t count) {
     if (i < count) out[i] = in[i];
 }
 
-hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream) {
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt, int hints) {
     const uint64_t nvec = bytes / 16;
     if (nvec) {
-        const uint64_t grid = (nvec + 1023) / 1024;
-        hipLaunchKernelGGL(k_copy, dim3((uint32_t)grid), dim3(256), 0, stream, (const u32x4*)in,
-                           (u32x4*)out, nvec);
+        const uint64_t per = 256ull * (uint64_t)vpt;
+        const dim3 grid((uint32_t)((nvec + per - 1) / per));
+        const u32x4* i4 = (const u32x4*)in;
+        u32x4* o4 = (u32x4*)out;
+#define BMMC_COPY(V)                                                                                  \
+    case V:                                                                                           \
+        switch (hints) {                                                                              \
+            case 0: hipLaunchKernelGGL((k_copy<V, 0>), grid, dim3(256), 0, stream, i4, o4, nvec); break; \
+            case 1: hipLaunchKernelGGL((k_copy<V, 1>), grid, dim3(256), 0, stream, i4, o4, nvec); break; \
+            case 2: hipLaunchKernelGGL((k_copy<V, 2>), grid, dim3(256), 0, stream, i4, o4, nvec); break; \
+            default: hipLaunchKernelGGL((k_copy<V, 3>), grid, dim3(256), 0, stream, i4, o4, nvec); break; \
+        }                                                                                             \
+        break;
+        switch (vpt) {
+            BMMC_COPY(1)
+            BMMC_COPY(2)
+            BMMC_COPY(8)
+            default:
+            BMMC_COPY(4)
+        }
+#undef BMMC_COPY
     }
     const uint32_t tail = (uint32_t)(bytes % 16);
     if (tail)
@@ -370,16 +422,12 @@ int batched_occupancy() {
     return blocks > 0 ? blocks : 1;
 }
 
-int tiled_occupancy(int w, int nt, int iters) {
-    for (const auto& e : kTiled) {
-        if (e.w == w && e.nt == nt && e.iters == iters) {
-            int blocks = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, e.fn, nt, 0) != hipSuccess)
-                return 1;
-            return blocks > 0 ? blocks : 1;
-        }
-    }
-    return 1;
+int tiled_occupancy(int w, int nt, int iters, int hints) {
+    const TiledEntry* e = find_tiled(w, nt, iters, hints);
+    if (!e) return 1;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, e->fn, nt, 0) != hipSuccess) return 1;
+    return blocks > 0 ? blocks : 1;
 }
 
 }  // namespace bmmc

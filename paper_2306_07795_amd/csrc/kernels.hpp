@@ -15,13 +15,16 @@ struct NaiveArgs {
     uint32_t col[kMaxTbBits];
 };
 
-// True when a tiled kernel exists for (w, nt, iters).
-bool tiled_kernel_available(int w, int nt, int iters);
+// True when a tiled kernel exists for (w, nt, iters, hints); hints bit 0
+// selects non-temporal loads, bit 1 non-temporal stores.
+bool tiled_kernel_available(int w, int nt, int iters, int hints = 0);
 
 // One LDS-staged pass over `ntiles` tiles with `grid` work-groups
 // (grid-stride over tiles).  in/out are 16-byte aligned device pointers.
-hipError_t launch_tiled(int w, int nt, int iters, const void* in, void* out,
-                        const PassTables& tab, uint32_t ntiles, uint32_t grid,
+// xcds > 0: give each of the xcds XCDs (which receive work-groups
+// round-robin) a contiguous range of tiles.
+hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, void* out,
+                        const PassTables& tab, uint32_t ntiles, uint32_t grid, uint32_t xcds,
                         hipStream_t stream);
 
 // Naive kernel: 2^n elements, one 16-byte vector (or one element when
@@ -29,8 +32,10 @@ hipError_t launch_tiled(int w, int nt, int iters, const void* in, void* out,
 hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs& args,
                         hipStream_t stream);
 
-// 16-byte vector copy of `bytes` bytes (tail handled bytewise).
-hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream);
+// 16-byte vector copy of `bytes` bytes (tail handled bytewise), vpt vectors
+// per lane (1, 2, 4, 8).
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt = 4,
+                       int hints = 0);
 
 // Batched persistent kernel (batched.hip).
 // passes / items / nitems / counters / head are device pointers; counters and
@@ -41,7 +46,7 @@ hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const
                           uint32_t grid, uint32_t spin_limit, hipStream_t stream);
 // Resident work-groups per CU of the batched kernel / of a tiled kernel.
 int batched_occupancy();
-int tiled_occupancy(int w, int nt, int iters);
+int tiled_occupancy(int w, int nt, int iters, int hints = 0);
 // Shape of the batched kernel's tile for an element width.
 inline int batched_iters() { return 4; }
 inline int batched_threads() { return 256; }

@@ -148,7 +148,7 @@ KernelShape default_shape(int w) {
 int default_t(const KernelShape& ks) { return ks.D() / 2; }
 
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
-               uint64_t seed, PassPlan* p) {
+               uint64_t seed, PassPlan* p, int tb_mix) {
     const int n = T.n;
     const int D = ks.D();
     BitMat Ti;
@@ -317,10 +317,23 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
             if ((lowbits >> k) & 1ull) g ^= tab.G[k];
         return g;
     };
+    // Tile-selecting vectors: the complement's index bits, or (tb_mix) each
+    // XOR-ed with a random choice of the higher ones -- an invertible change
+    // of basis of the same complement, which changes which tiles run
+    // together but not what any tile holds.
+    uint64_t tbv[kMaxBits];
+    for (int i = 0; i < ntb; i++) tbv[i] = 1ull << tbpos[i];
+    if (tb_mix) {
+        uint64_t s = seed ^ 0x7B1Dull;
+        for (int i = 0; i < ntb; i++) {
+            s = mix64(s);
+            for (int j = i + 1; j < ntb; j++)
+                if ((s >> (j & 63)) & 1ull) tbv[i] ^= 1ull << tbpos[j];
+        }
+    }
     for (int i = 0; i < ntb; i++) {
-        int j = tbpos[i];
-        uint64_t col = T.col(j);
-        tab.tb_in[i] = 1u << j;
+        uint64_t col = T.apply(tbv[i]);
+        tab.tb_in[i] = (uint32_t)tbv[i];
         tab.tb_out[i] = (uint32_t)(col & ~low_mask(b));
         tab.tb_lds[i] = gmap(col & low_mask(b));
     }
@@ -358,23 +371,26 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
     }
     const int D = ks.D();
     int t = opt.t > 0 ? opt.t : default_t(ks);
-    if (t < ks.lv() || t > D) return BMMC_ERR_RANGE;
+    const int a = opt.a > 0 ? opt.a : t;  // read runs of 2^a elements
+    const int b = opt.b > 0 ? opt.b : t;  // write runs of 2^b elements
+    if (a < ks.lv() || b < ks.lv() || a > D || b > D) return BMMC_ERR_RANGE;
     p->t = t;
     uint64_t seed = 0x243F6A8885A308D3ull ^ ((uint64_t)n << 32) ^ (uint64_t)w;
     int st;
-    if (opt.method == kMethodOnePass || n <= D || is_tiled(A, t)) {
-        // One pass: the whole array fits a tile, A is tiled, or the caller
-        // asked for a general tile.
-        st = build_pass(A, c, t, t, ks, opt.swizzle, seed, &p->pass[0]);
+    if (opt.method == kMethodOnePass || n <= D || is_tiled(A, b)) {
+        // One pass: the whole array fits a tile, A is tiled (its inputs that
+        // reach the low b output bits are index bits), or the caller asked
+        // for a general tile.
+        st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix);
         if (st != BMMC_OK) return st;
         p->npass = 1;
         return BMMC_OK;
     }
     BitMat T1, T2;
     if (!factorize_ulp(A, nullptr, nullptr, nullptr, &T1, &T2)) return BMMC_ERR_SINGULAR;
-    st = build_pass(T2, 0, t, t, ks, opt.swizzle, seed, &p->pass[0]);
+    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix);
     if (st != BMMC_OK) return st;
-    st = build_pass(T1, c, t, t, ks, opt.swizzle, seed + 1, &p->pass[1]);
+    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix);
     if (st != BMMC_OK) return st;
     p->npass = 2;
     return BMMC_OK;

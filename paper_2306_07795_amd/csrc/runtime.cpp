@@ -3,6 +3,7 @@
 #include "runtime.hpp"
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "kernels.hpp"
@@ -26,8 +27,8 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 bool PlanKey::operator==(const PlanKey& o) const {
-    if (n != o.n || w != o.w || method != o.method || t != o.t || nt != o.nt || iters != o.iters ||
-        swizzle != o.swizzle || c != o.c)
+    if (n != o.n || w != o.w || method != o.method || t != o.t || a != o.a || b != o.b || nt != o.nt ||
+        iters != o.iters || swizzle != o.swizzle || tb_mix != o.tb_mix || c != o.c)
         return false;
     for (int i = 0; i < n; i++)
         if (rows[i] != o.rows[i]) return false;
@@ -42,8 +43,9 @@ size_t PlanKeyHash::operator()(const PlanKey& k) const {
         h ^= h >> 29;
     };
     mixin((uint64_t)k.n | ((uint64_t)k.w << 8) | ((uint64_t)k.method << 16) | ((uint64_t)k.t << 24) |
-          ((uint64_t)k.nt << 32) | ((uint64_t)k.iters << 48) | ((uint64_t)k.swizzle << 60));
-    mixin(k.c);
+          ((uint64_t)k.nt << 32) | ((uint64_t)k.iters << 48) | ((uint64_t)k.swizzle << 60) |
+          ((uint64_t)k.tb_mix << 62));
+    mixin(k.c ^ ((uint64_t)k.a << 56) ^ ((uint64_t)k.b << 48));
     for (int i = 0; i < k.n; i++) mixin(k.rows[i]);
     return (size_t)h;
 }
@@ -65,6 +67,7 @@ DeviceState* device_state(int* status) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
         s->cu_count = cus;
+        if (const char* x = std::getenv("BMMC_XCDS")) s->xcds = std::atoi(x) > 0 ? std::atoi(x) : 8;
         states[dev] = s;
     }
     *status = BMMC_OK;
@@ -81,9 +84,12 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
     key.w = w;
     key.method = o.method;
     key.t = o.t;
+    key.a = o.a;
+    key.b = o.b;
     key.nt = o.shape.nt;
     key.iters = o.shape.iters;
     key.swizzle = o.swizzle;
+    key.tb_mix = o.tb_mix;
     key.c = c;
     for (int i = 0; i < n; i++) key.rows[i] = rows[i];
     {
@@ -162,7 +168,10 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     if (!o) return p;
     p.method = o->method;
     p.t = o->t;
+    p.a = o->run_in;
+    p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
+    p.tb_mix = (o->tile_order >> 1) & 1;
     if (o->threads > 0) p.shape.nt = o->threads;
     if (o->iters > 0) p.shape.iters = o->iters;
     return p;
@@ -174,7 +183,7 @@ static void kernel_name(char* buf, size_t len, const Plan& p) {
 }
 
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
-                 uint32_t grid) {
+                 uint32_t grid, int hints, int order) {
     const size_t bytes = ((size_t)1 << plan.n) * (size_t)plan.w;
     hipError_t e;
     if (plan.npass == 0) {
@@ -193,8 +202,9 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "naive launch");
     }
     const KernelShape& ks = plan.shape;
-    if (!tiled_kernel_available(plan.w, ks.nt, ks.iters))
-        return set_error(BMMC_ERR_RANGE, "no tiled kernel for w=%d threads=%d iters=%d", plan.w, ks.nt, ks.iters);
+    if (!tiled_kernel_available(plan.w, ks.nt, ks.iters, hints))
+        return set_error(BMMC_ERR_RANGE, "no tiled kernel for w=%d threads=%d iters=%d hints=%d", plan.w, ks.nt,
+                         ks.iters, hints);
     void* mid = nullptr;
     if (plan.npass == 2) {
         int st = get_scratch(ds, stream, bytes, &mid);
@@ -208,7 +218,8 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         const uint32_t ntiles = 1u << tab.ntb;
         kernel_name(name, sizeof(name), plan);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
-        e = launch_tiled(plan.w, ks.nt, ks.iters, src, dst, tab, ntiles, grid, stream);
+        e = launch_tiled(plan.w, ks.nt, ks.iters, hints, src, dst, tab, ntiles, grid,
+                         (order & 1) ? (uint32_t)ds->xcds : 0u, stream);
         if (e != hipSuccess) return hip_fail(e, "tiled launch");
     }
     return BMMC_OK;
@@ -356,7 +367,8 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     st = get_plan(ds, A_rows, c, n, elem_bytes, po, &plan);
     if (st != BMMC_OK) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
-    return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, opts ? (uint32_t)opts->grid : 0);
+    return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, opts ? (uint32_t)opts->grid : 0,
+                        opts ? (opts->hints & 3) : 0, opts ? opts->tile_order : 0);
 }
 
 int bmmc_permute(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
@@ -372,15 +384,21 @@ int bmmc_permute_naive(const void* in, void* out, int n, const uint64_t* A_rows,
     return bmmc_permute_ex(in, out, n, A_rows, c, elem_bytes, &o, stream);
 }
 
-int bmmc_copy(const void* in, void* out, size_t bytes, void* stream) {
+int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, void* stream) {
     int st = validate_buffers(in, out, bytes);
     if (st != BMMC_OK) return st;
+    if (!(vpt == 1 || vpt == 2 || vpt == 4 || vpt == 8) || hints < 0 || hints > 3)
+        return set_error(BMMC_ERR_ARG, "vpt must be 1, 2, 4 or 8 and hints 0..3");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
     LaunchScope ls(ds, (hipStream_t)stream, "k_copy", 2.0 * (double)bytes);
-    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream);
+    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
+}
+
+int bmmc_copy(const void* in, void* out, size_t bytes, void* stream) {
+    return bmmc_copy_ex(in, out, bytes, 4, 0, stream);
 }
 
 int bmmc_profile_begin(void) {

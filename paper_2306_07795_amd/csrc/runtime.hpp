@@ -19,7 +19,7 @@ int set_error(int status, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 
 struct PlanKey {
-    int n, w, method, t, nt, iters, swizzle;
+    int n, w, method, t, a, b, nt, iters, swizzle, tb_mix;
     uint64_t c;
     uint64_t rows[kMaxBits];
     bool operator==(const PlanKey& o) const;
@@ -37,6 +37,7 @@ struct ProfileEvent {
 struct DeviceState {
     int device = 0;
     int cu_count = 0;
+    int xcds = 8;  // work-groups are dealt round-robin to this many XCDs
     std::mutex mu;
     std::unordered_map<PlanKey, std::shared_ptr<const Plan>, PlanKeyHash> plans;
     struct Scratch {
@@ -73,7 +74,7 @@ PlanOptions plan_options(const bmmc_options_t* o, int w);
 
 // Enqueue the passes of a plan (caller holds ds->mu).
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
-                 uint32_t grid);
+                 uint32_t grid, int hints = 0, int order = 0);
 
 int validate_buffers(const void* in, const void* out, size_t bytes);
 

@@ -1,0 +1,219 @@
+"""Batched and served forms on the GPU against the oracle, through the C ABI.
+
+Each array's output must equal the oracle's, bit for bit, whether it runs in
+one batched persistent launch, through graph replays, alone, or mixed with
+other requests in the continuous-batching server.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2306_07795_amd import binding as B
+from synth import gen
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(sizes, widths, seed):
+    arrays = []
+    for k, (n, w) in enumerate(zip(sizes, widths)):
+        rows, c = gen.random_bmmc(n, seed * 10007 + k)
+        a = gen.data(n, w, seed * 10007 + k)
+        arrays.append({"n": n, "w": w, "rows": rows, "c": c, "a": a,
+                       "x": G.to_device(a), "y": G.empty_like_bytes(a)})
+    return arrays
+
+
+def items(arrays):
+    return [(ar["x"], ar["y"], ar["n"], ar["w"], ar["rows"], ar["c"]) for ar in arrays]
+
+
+def check_all(arrays):
+    for k, ar in enumerate(arrays):
+        got = G.to_host(ar["y"], ar["a"])
+        want = O.permute(ar["a"], ar["n"], ar["rows"], ar["c"])
+        assert np.array_equal(got, want), f"array {k}: n={ar['n']} w={ar['w']}"
+
+
+@pytest.mark.parametrize("use_graph", [1, -1])
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_batched_mixed_sizes_and_widths(order, use_graph):
+    rng = np.random.default_rng(order)
+    sizes = [int(v) for v in rng.integers(0, 19, size=48)]
+    widths = [int(v) for v in rng.choice([4, 8, 16, 1, 2], size=48)]
+    arrays = make_batch(sizes, widths, 3 + order)
+    B.bmmc_permute_batched(items(arrays), G.stream(),
+                           {"order": order, "use_graph": use_graph, "chunk_tiles": 1 + order})
+    assert not B.bmmc_batched_status(G.stream())
+    check_all(arrays)
+
+
+@pytest.mark.parametrize("chunk", [1, 4, 16])
+def test_batched_chunks_and_grid(chunk):
+    sizes = gen.batched_sizes(40, chunk, 10, 20)
+    arrays = make_batch(sizes, [4] * len(sizes), chunk)
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"chunk_tiles": chunk, "workgroups": 64})
+    assert not B.bmmc_batched_status(G.stream())
+    check_all(arrays)
+
+
+def test_batched_onepass_method():
+    sizes = gen.batched_sizes(32, 9, 10, 21)
+    arrays = make_batch(sizes, [4, 8] * 16, 9)
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"method": B.METHOD_ONEPASS})
+    check_all(arrays)
+
+
+def test_graph_replays_with_fresh_data():
+    """The same batch shape replayed from the cached graph, with new inputs
+    and eager work in between; every replay is checked."""
+    sizes = gen.batched_sizes(24, 5, 10, 19)
+    arrays = make_batch(sizes, [4] * len(sizes), 5)
+    for rep in range(4):
+        for k, ar in enumerate(arrays):
+            ar["a"] = gen.data(ar["n"], 4, 1000 * rep + k)
+            ar["x"].copy_(torch.from_numpy(ar["a"].view(np.uint8)).to(G.dev()))
+            ar["y"].zero_()
+        torch.cuda.synchronize()
+        B.bmmc_permute_batched(items(arrays), G.stream())
+        assert not B.bmmc_batched_status(G.stream())
+        check_all(arrays)
+
+
+def test_batch_of_1024_like_the_workload():
+    """1024 arrays, n uniform in [10, 22], int32, each with its own A and c
+    (the batched workload's shape); every array checked on sampled outputs
+    and the smallest hundred in full."""
+    sizes = gen.batched_sizes(1024, 0, 10, 22)
+    arrays = []
+    for k, n in enumerate(sizes):
+        rows, c = gen.random_bmmc(n, k)
+        a = gen.data(n, 4, k)
+        arrays.append({"n": n, "w": 4, "rows": rows, "c": c, "a": a,
+                       "x": G.to_device(a), "y": G.empty_like_bytes(a)})
+    B.bmmc_permute_batched(items(arrays), G.stream())
+    assert not B.bmmc_batched_status(G.stream())
+    rng = np.random.default_rng(0)
+    order = sorted(range(len(arrays)), key=lambda k: arrays[k]["n"])
+    for rank, k in enumerate(order):
+        ar = arrays[k]
+        got = G.to_host(ar["y"], ar["a"])
+        if rank < 100:
+            assert np.array_equal(got, O.permute(ar["a"], ar["n"], ar["rows"], ar["c"]))
+        else:
+            xs = rng.integers(0, 1 << ar["n"], size=512, dtype=np.uint64)
+            ys = O.apply_many(ar["rows"], ar["c"], ar["n"], xs).astype(np.int64)
+            assert np.array_equal(got[ys], ar["a"][xs.astype(np.int64)]), f"array {k}"
+
+
+def test_batched_equals_separate_calls():
+    sizes = gen.batched_sizes(16, 2, 12, 20)
+    arrays = make_batch(sizes, [8] * 16, 2)
+    B.bmmc_permute_batched(items(arrays), G.stream())
+    torch.cuda.synchronize()
+    for ar in arrays:
+        z = G.empty_like_bytes(ar["a"])
+        B.bmmc_permute(ar["x"], z, ar["n"], ar["rows"], ar["c"], ar["w"], G.stream())
+        torch.cuda.synchronize()
+        assert torch.equal(z, ar["y"])
+
+
+def test_autotune_small_then_permute():
+    opts, ms = B.bmmc_autotune(18, 4, B.METHOD_AUTO, G.stream(), 2)
+    assert ms > 0 and opts["threads"] in (256, 512, 1024)
+    rows, c = gen.random_bmmc(18, 4)
+    a = gen.data(18, 4, 4)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    B.bmmc_permute(x, y, 18, rows, c, 4, G.stream())  # now uses the tuned shape
+    G.sync()
+    assert np.array_equal(G.to_host(y, a), O.permute(a, 18, rows, c))
+
+
+def test_autotune_batched_small():
+    sizes = gen.batched_sizes(20, 11, 10, 16)
+    arrays = make_batch(sizes, [4] * 20, 11)
+    opts, ms = B.bmmc_autotune_batched(items(arrays), G.stream(), 1)
+    assert ms > 0 and opts["chunk_tiles"] >= 1
+    for ar in arrays:
+        ar["y"].zero_()
+    B.bmmc_permute_batched(items(arrays), G.stream())  # tuned options
+    check_all(arrays)
+
+
+# ------------------------------------------------------------------ server
+
+def test_server_mix_equals_alone_equals_oracle():
+    reqs = gen.poisson_requests(60, 20000.0, 7, n_lo=8, n_hi=20)
+    pool = {}
+    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True)
+    try:
+        t0 = B.bmmc_server_now_ns() + 2_000_000
+        tickets = []
+        for r in reqs:
+            rows, c = gen.random_bmmc(r["n"], r["seed"])
+            a = gen.data(r["n"], r["w"], r["seed"])
+            x = G.to_device(a)
+            pool[r["id"]] = (rows, c, a, x)
+            tickets.append(B.bmmc_server_submit(srv, x, 0, r["n"], rows, c, r["w"],
+                                                t0 + int(r["arrival"] * 1e9)))
+        torch.cuda.synchronize()
+        B.bmmc_server_drain(srv)
+        mixed = {}
+        for r, tk in zip(reqs, tickets):
+            done, out = B.bmmc_server_poll(srv, tk)
+            rows, c, a, x = pool[r["id"]]
+            y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+            B.bmmc_copy(out, y, a.nbytes, G.stream())
+            G.sync()
+            got = G.to_host(y, a)
+            assert np.array_equal(got, O.permute(a, r["n"], rows, c)), r
+            mixed[r["id"]] = got
+            B.bmmc_server_release(srv, tk)
+        st = B.bmmc_server_stats(srv)
+        assert st["completed"] == len(reqs) and st["rejected"] == 0
+        assert st["p99_ms"] >= st["p50_ms"] > 0
+    finally:
+        B.bmmc_server_destroy(srv)
+    # the same requests alone, one server each time
+    srv = B.bmmc_server_create(1 << 28, streams=1, own_outputs=True)
+    try:
+        for r in reqs[:12]:
+            rows, c, a, x = pool[r["id"]]
+            tk = B.bmmc_server_submit(srv, x, 0, r["n"], rows, c, r["w"])
+            done, out = B.bmmc_server_poll(srv, tk, wait=True)
+            y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+            B.bmmc_copy(out, y, a.nbytes, G.stream())
+            G.sync()
+            assert np.array_equal(G.to_host(y, a), mixed[r["id"]])
+            B.bmmc_server_release(srv, tk)
+    finally:
+        B.bmmc_server_destroy(srv)
+
+
+def test_server_budget_admission_and_caller_outputs():
+    """A budget that admits one large request at a time still completes all,
+    in order; outputs provided by the caller."""
+    n, w = 20, 4
+    srv = B.bmmc_server_create(3 * (1 << n) * w + (1 << 20), streams=2, own_outputs=False)
+    try:
+        work = []
+        for k in range(6):
+            rows, c = gen.random_bmmc(n, 50 + k)
+            a = gen.data(n, w, 50 + k)
+            x, y = G.to_device(a), G.empty_like_bytes(a)
+            torch.cuda.synchronize()
+            tk = B.bmmc_server_submit(srv, x, y, n, rows, c, w)
+            work.append((tk, rows, c, a, x, y))
+        B.bmmc_server_drain(srv)
+        for tk, rows, c, a, x, y in work:
+            B.bmmc_server_poll(srv, tk)
+            assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
+            B.bmmc_server_release(srv, tk)
+        st = B.bmmc_server_stats(srv)
+        assert st["peak_bytes"] <= 3 * (1 << n) * w + (1 << 20)
+        with pytest.raises(B.BmmcError):  # can never fit
+            B.bmmc_server_submit(srv, work[0][4], work[0][5], 22, gen.identity_rows(22), 0, 4)
+    finally:
+        B.bmmc_server_destroy(srv)

@@ -306,6 +306,8 @@ def test_emulation_methods(method, n):
     {"threads": 512, "iters": 4}, {"threads": 1024, "iters": 2}, {"threads": 256, "iters": 8},
     {"threads": 256, "iters": 2}, {"t": 5}, {"t": 4, "threads": 256, "iters": 2},
     {"swizzle": -1}, {"threads": 256, "iters": 16, "t": 7},
+    {"run_in": 7, "run_out": 5}, {"run_in": 5, "run_out": 7}, {"threads": 512, "run_in": 7, "run_out": 6},
+    {"tile_order": 2}, {"tile_order": 3, "run_in": 7, "run_out": 5},
 ])
 def test_emulation_shapes(opts):
     n = 17
