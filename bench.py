@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of BMMC permutations on one MI355X.
 
-Default workload: a uniformly random invertible 26 x 26 matrix over F_2 with
-a random complement (seed 0), applied to 2^26 int32 elements drawn from seed
-0 -- the paper's scheme, i.e. two LDS-staged tiled passes through scratch.
-One step is one whole permutation (both passes) of the resident array.
+Default workload: a uniformly random invertible 26 x 26 matrix over F_2 with a
+random complement (seed 0), applied to 2^26 int32 elements drawn from seed 0
+by the paper's scheme: factorization into two tiled BMMCs, each run as one
+LDS-staged pass (through a scratch array).  One step is one whole permutation
+(both passes) of the HBM-resident array.
 
 Prints ONE JSON line.  `value` is effective throughput in GB/s (decimal):
-algorithmic bytes (one read + one write of the array, 2 * 2^n * w) per step
-time.  Beside it: the same-session device-copy rate and HBM peak fractions,
-the traffic rate (bytes of both passes), the per-kernel roofline of the tiled
-pass, and the CPU oracle's rate on this host.
+algorithmic bytes (one read plus one write of the array, 2 * 2^n * w) per step
+time.  Beside it: the best same-session device copy and the HBM peak as
+fractions, the traffic rate (both passes' bytes, the paper's accounting), the
+roofline of the tiled-pass kernel, the general one-pass tile, the naive lower
+bound, the batched form (1024 arrays, one graph launch, against 1024 separate
+calls; p50/p99 of the batch latency), the served form (Poisson arrivals,
+p50/p99 request latency) and the CPU oracle's rate on this host.
 """
 from __future__ import annotations
 
@@ -29,12 +33,15 @@ HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
     # name: (n, elem_bytes, matrix kind, description)
-    "random26": (26, 4, "random", "random BMMC on 2^26 int32 (A uniform invertible 26x26 over F_2, random c, seed 0)"),
-    "random28": (28, 4, "random", "random BMMC on 2^28 int32 (seed 0)"),
-    "random27x8": (27, 8, "random", "random BMMC on 2^27 int64 (seed 0)"),
-    "bitrev28": (28, 4, "bitrev", "bit reversal of 2^28 int32"),
-    "swap28": (28, 4, "swap", "2^14 x 2^14 int32 matrix transpose (low/high bit-block swap)"),
-    "bitrev20": (20, 4, "bitrev", "bit reversal of 2^20 int32 (cache resident)"),
+    "random26": (26, 4, "random", "random BMMC on 2^26 int32 (A uniform invertible 26x26 over F_2, "
+                                  "random c, seed 0), two tiled passes"),
+    "random28": (28, 4, "random", "random BMMC on 2^28 int32 (seed 0), two tiled passes"),
+    "random27x8": (27, 8, "random", "random BMMC on 2^27 int64 (seed 0), two tiled passes"),
+    "bitrev28": (28, 4, "bitrev", "bit reversal of 2^28 int32, one tiled pass"),
+    "bitrev27x8": (27, 8, "bitrev", "bit reversal of 2^27 int64, one tiled pass"),
+    "swap28": (28, 4, "swap", "2^14 x 2^14 int32 matrix transpose (bit-block swap), one tiled pass"),
+    "swap27x8": (27, 8, "swap", "2^13 x 2^14 int64 matrix transpose (bit-block swap), one tiled pass"),
+    "bitrev20": (20, 4, "bitrev", "bit reversal of 2^20 int32 (cache resident), one tiled pass"),
 }
 
 
@@ -72,7 +79,11 @@ def timed(fn, steps, warmup, stream):
     return a.elapsed_time(b) / steps
 
 
-def cpu_baseline(a, n, rows, c, w, budget_s=12.0):
+def gbps(nbytes, ms):
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(a, n, rows, c, budget_s=12.0):
     """The oracle, as is, on this host's cores: repeats of the full workload
     until about budget_s seconds have passed (at least one)."""
     from oracle import oracle as orc
@@ -89,7 +100,7 @@ def cpu_baseline(a, n, rows, c, w, budget_s=12.0):
             "sample": f"the full workload (2^{n} elements), {reps} repetition(s), {dt:.2f} s each"}
 
 
-def traffic_for(kernel, launch_bytes):
+def traffic_for(kernel):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken
     on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -99,9 +110,111 @@ def traffic_for(kernel, launch_bytes):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     ent = rec.get("kernels", {}).get(kernel)
-    if not ent:
-        return None
-    return ent.get("bytes_per_launch")
+    return ent.get("bytes_per_launch") if ent else None
+
+
+def best_device_copy(x, y, nbytes, stream):
+    """Fastest of the copy kernel's variants and hipMemcpy (device to device)."""
+    from paper_2306_07795_amd import binding as B
+    best = (1e30, None)
+    for vpt in (1, 2, 4, 8):
+        for hints in (0, 1, 2, 3):
+            ms = timed(lambda: B.bmmc_copy_ex(x, y, nbytes, vpt, hints, stream), 10, 2, stream)
+            best = min(best, (ms, f"k_copy vpt={vpt} hints={hints}"))
+    ms = timed(lambda: y.copy_(x), 10, 2, stream)
+    best = min(best, (ms, "hipMemcpy device to device"))
+    return best
+
+
+def bench_batched(count=1024, reps=50, seed=0):
+    """1024 arrays, n uniform in [10, 22], int32, each its own A and c: one
+    graph-launched persistent kernel against 1024 separate bmmc_permute calls
+    on one stream.  Batch latency = one launch's events; p50/p99 over reps."""
+    import numpy as np
+    import torch
+    from paper_2306_07795_amd import binding as B
+    from synth import gen
+    sizes = gen.batched_sizes(count, seed, 10, 22)
+    items, total = [], 0
+    for k, n in enumerate(sizes):
+        rows, c = gen.random_bmmc(n, 1_000_003 * (seed + 1) + k)
+        x = torch.randint(0, 1 << 30, (1 << n,), dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        items.append((x, y, n, 4, rows, c))
+        total += (1 << n) * 4
+    stream = torch.cuda.current_stream()
+    tuned, tune_ms = B.bmmc_autotune_batched(items, stream, 2)
+
+    def lat(fn, r):
+        out = []
+        for _ in range(r):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return np.array(out)
+
+    batched = lat(lambda: B.bmmc_permute_batched(items, stream), reps)
+
+    def separate():
+        for it in items:
+            B.bmmc_permute(it[0], it[1], it[2], it[4], it[5], 4, stream)
+
+    sep = lat(separate, max(5, reps // 5))
+    assert not B.bmmc_batched_status(stream)
+    med = float(np.median(batched))
+    return {
+        "arrays": count, "bytes_per_side": total,
+        "GBps": round(gbps(total, med), 1),
+        "p50_ms": round(med, 4), "p99_ms": round(float(np.percentile(batched, 99)), 4),
+        "separate_launches_GBps": round(gbps(total, float(np.median(sep))), 1),
+        "separate_p50_ms": round(float(np.median(sep)), 4),
+        "separate_p99_ms": round(float(np.percentile(sep, 99)), 4),
+        "speedup_vs_separate": round(float(np.median(sep)) / med, 2),
+        "tuned": tuned,
+    }
+
+
+def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0):
+    """Open-loop Poisson arrivals at `rate` requests/s for `seconds`: n uniform
+    in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs resident in
+    a pool per (n, width); outputs and scratch from the server's HBM budget."""
+    import torch
+    from paper_2306_07795_amd import binding as B
+    from synth import gen
+    count = int(rate * seconds)
+    reqs = gen.poisson_requests(count, rate, seed, 12, 26, (4, 8))
+    pool = {}
+    for n in range(12, 27):
+        for w in (4, 8):
+            pool[(n, w)] = torch.randint(0, 255, ((1 << n) * w,), dtype=torch.uint8, device="cuda")
+    mats = {}
+    for r in reqs:
+        mats[r["id"]] = gen.random_bmmc(r["n"], r["seed"])
+    torch.cuda.synchronize()
+    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2)
+    try:
+        start = B.bmmc_server_now_ns() + int(0.5e9)
+        for r in reqs:
+            rows, c = mats[r["id"]]
+            B.bmmc_server_submit(srv, pool[(r["n"], r["w"])], 0, r["n"], rows, c, r["w"],
+                                 start + int(r["arrival"] * 1e9))
+        B.bmmc_server_drain(srv)
+        st = B.bmmc_server_stats(srv)
+    finally:
+        B.bmmc_server_destroy(srv)
+    offered = sum((1 << r["n"]) * r["w"] for r in reqs)
+    return {
+        "rate_req_s": rate, "requests": count, "completed": st["completed"], "rejected": st["rejected"],
+        "GBps": round(st["bytes_moved"] / max(st["busy_s"], 1e-9) / 1e9, 1),
+        "offered_GBps": round(2.0 * offered / (reqs[-1]["arrival"]) / 1e9, 1),
+        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+        "mean_batch": round(st["mean_batch"], 1), "launches": st["batches"],
+        "peak_budget_GB": round(st["peak_bytes"] / 1e9, 2),
+    }
 
 
 def main():
@@ -111,7 +224,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="random26", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="auto", choices=["auto", "onepass", "naive"])
+    ap.add_argument("--no-tune", action="store_true", help="time the library defaults, no autotuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-rate", type=float, default=20000.0)
+    ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--extras-out", default=None, help="write extra measurements (JSON) here")
     args = ap.parse_args()
 
@@ -138,7 +256,13 @@ def main():
     x = torch.from_numpy(a.view(np.uint8).reshape(-1)).to(dev)
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+
     opts = {"method": method}
+    tuned = None
+    if not args.no_tune and method != B.METHOD_NAIVE:
+        tuned, _ = B.bmmc_autotune(n, w, method, stream, 3)
+        opts = dict(tuned)
+        opts["method"] = method
 
     def step():
         B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
@@ -169,32 +293,31 @@ def main():
     torch.cuda.synchronize()
     kstats = B.bmmc_profile_end()
     ms = ev0.elapsed_time(ev1) / args.steps
-    value = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    value = gbps(nbytes, ms)
 
-    # bounds in the same session: copy kernel, hipMemcpy D2D, naive kernel
-    copy_ms = timed(lambda: B.bmmc_copy(x, y, nbytes, stream), 20, 3, stream)
-    d2d_ms = timed(lambda: y.copy_(x), 20, 3, stream)
-    dev_copy_gbps = 2.0 * nbytes / (min(copy_ms, d2d_ms) * 1e-3) / 1e9
-    extras = {
-        "copy_kernel_GBps": round(2.0 * nbytes / (copy_ms * 1e-3) / 1e9, 1),
-        "hipmemcpy_d2d_GBps": round(2.0 * nbytes / (d2d_ms * 1e-3) / 1e9, 1),
-    }
+    # bounds in the same session
+    copy_ms, copy_how = best_device_copy(x, y, nbytes, stream)
+    dev_copy = gbps(nbytes, copy_ms)
+    extras = {"device_copy": copy_how}
     if method == B.METHOD_AUTO:
         naive_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, c, w, stream), 10, 2, stream)
-        one_ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, {"method": B.METHOD_ONEPASS},
-                                                 stream), 20, 3, stream)
-        extras["naive_GBps"] = round(2.0 * nbytes / (naive_ms * 1e-3) / 1e9, 1)
-        extras["onepass_GBps"] = round(2.0 * nbytes / (one_ms * 1e-3) / 1e9, 1)
-        extras["onepass_pct_of_device_copy"] = round(100.0 * extras["onepass_GBps"] / dev_copy_gbps, 2)
+        extras["naive_GBps"] = round(gbps(nbytes, naive_ms), 1)
+        one_opts = {"method": B.METHOD_ONEPASS}
+        if not args.no_tune:
+            one_opts, _ = B.bmmc_autotune(n, w, B.METHOD_ONEPASS, stream, 3)
+            one_opts["method"] = B.METHOD_ONEPASS
+        one_ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, one_opts, stream), 20, 3, stream)
+        extras["onepass_GBps"] = round(gbps(nbytes, one_ms), 1)
+        extras["onepass_pct_of_device_copy"] = round(100.0 * gbps(nbytes, one_ms) / dev_copy, 2)
+        extras["onepass_pct_of_hbm_peak"] = round(100.0 * gbps(nbytes, one_ms) / HBM_PEAK_GBPS, 2)
 
     # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
-    dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
-    dname, d = dom
+    dname, d = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
     per_launch_ms = d["total_ms"] / d["launches"]
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dname, launch_bytes),
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dname),
                 "kernel": dname, "launches": d["launches"], "mean_launch_ms": round(per_launch_ms, 5),
                 "bytes_per_launch": launch_bytes}
 
@@ -204,17 +327,25 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "elem_bytes": w, "method": args.method,
-                   "passes": passes, "seed": 0},
-        "pct_of_device_copy": round(100.0 * value / dev_copy_gbps, 2),
+                   "passes": passes, "seed": 0, "options": tuned},
+        "pct_of_device_copy": round(100.0 * value / dev_copy, 2),
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
-        "device_copy_GBps": round(dev_copy_gbps, 1),
+        "device_copy_GBps": round(dev_copy, 1),
         "traffic_GBps": round(value * passes, 2),
-        "traffic_pct_of_device_copy": round(100.0 * value * passes / dev_copy_gbps, 2),
+        "traffic_pct_of_device_copy": round(100.0 * value * passes / dev_copy, 2),
         "roofline": roofline,
         "extras": extras,
     }
+    del x, y
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = bench_batched()
+        torch.cuda.empty_cache()
+    if not args.no_served:
+        line["served"] = bench_served(args.served_rate, args.served_seconds)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(a, n, rows, c, w)
+        line["cpu_baseline"] = cpu_baseline(a, n, rows, c)
     if args.extras_out:
         with open(args.extras_out, "w") as f:
             json.dump({"kernels": kstats, **extras}, f, indent=1)

@@ -72,7 +72,7 @@ typedef enum {
     BMMC_METHOD_NAIVE = 3
 } bmmc_method;
 
-/* Tuning knobs of one call; zero means "library default". */
+/* Tuning knobs of one call; zero means "library default" everywhere. */
 typedef struct {
     int method;    /* bmmc_method */
     int t;         /* run bits: reads and writes move runs of 2^t elements */
@@ -82,10 +82,13 @@ typedef struct {
     int grid;      /* work-groups per pass launch; 0 = one per tile */
     int run_in;    /* read-run bits (input runs of 2^run_in elements); 0 = t */
     int run_out;   /* write-run bits (output runs of 2^run_out elements); 0 = t */
-    int hints;     /* bit 0: non-temporal loads, bit 1: non-temporal stores */
-    /* bit 0: give each XCD a contiguous range of tiles (work-groups are
-       dealt to the 8 XCDs round-robin); bit 1: select tiles through mixed
-       (XOR-combined) index bits instead of plain index bits. */
+    /* 1: non-temporal loads, 2: non-temporal stores, 3: both, 4: neither;
+       0: both for arrays of 64 MiB and more, neither below. */
+    int hints;
+    /* 1: give each XCD a contiguous range of tiles (work-groups are dealt
+       to the XCDs round-robin); 2: select tiles through XOR-combined index
+       bits; 3: both; 4: neither; 0: 2 for one-pass plans of tiled matrices
+       larger than a tile, 4 otherwise. */
     int tile_order;
     int reserved[2];
 } bmmc_options_t;
@@ -215,7 +218,9 @@ int bmmc_permute_naive(const void* in, void* out, int n, const uint64_t* A_rows,
    16-byte vector loads and stores.  Pointers must not overlap. */
 int bmmc_copy(const void* in, void* out, size_t bytes, void* stream);
 /* The same copy with a chosen kernel: vpt 16-byte vectors per lane (1, 2, 4
-   or 8), hints as in bmmc_options_t.  bmmc_copy uses vpt = 4, hints = 0. */
+   or 8); hints bit 0 makes the loads and bit 1 the stores non-temporal.
+   bmmc_copy uses vpt = 2 with non-temporal stores for 64 MiB and more,
+   vpt = 4 without hints below. */
 int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, void* stream);
 
 /* Many independent permutations, each with its own n, width, A and c, in one
@@ -285,7 +290,8 @@ typedef struct {
 
 /* A continuous-batching server on the current device.  It allocates one
    device arena (the largest power of two <= budget_bytes) for outputs and
-   scratch, `streams` HIP streams at default priority, and two host threads.
+   scratch, `streams` HIP streams at default priority, four planner threads
+   and one dispatcher thread.
    Requests are admitted in arrival order while input + output + scratch of
    all admitted, unfinished requests fits budget_bytes; every admitted request
    joins the next batched launch on a free stream.

@@ -354,12 +354,14 @@ def bmmc_tune_load(path: str):
 # ---------------------------------------------------------------- serving
 
 def bmmc_server_create(budget_bytes: int, streams: int = 4, max_batch: int = 0,
-                       own_outputs: bool = True, method: int = METHOD_AUTO):
+                       own_outputs: int = 1, method: int = METHOD_AUTO):
+    """own_outputs: 0 caller passes out, 1 server allocates and keeps it until
+    release, 2 server allocates and drops it at completion."""
     o = ServerOptions()
     o.budget_bytes = budget_bytes
     o.streams = streams
     o.max_batch = max_batch
-    o.own_outputs = 1 if own_outputs else 0
+    o.own_outputs = int(own_outputs)
     o.method = method
     h = _vp()
     _check(lib().bmmc_server_create(_c.byref(o), _c.byref(h)))

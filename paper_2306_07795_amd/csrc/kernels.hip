@@ -170,13 +170,13 @@ struct TiledEntry {
         {W, NT, IT, 2, k_tiled<W, NT, IT, 2>}, {W, NT, IT, 3, k_tiled<W, NT, IT, 3>}
 static const TiledEntry kTiled[] = {
     BMMC_TILED_H(4, 256, 4),  BMMC_TILED_H(4, 512, 4),  BMMC_TILED_H(4, 256, 8), BMMC_TILED_H(4, 512, 2),
-    BMMC_TILED(4, 256, 2),    BMMC_TILED(4, 1024, 2),   BMMC_TILED(4, 1024, 4),  BMMC_TILED(4, 256, 16),
-    BMMC_TILED(4, 512, 8),
-    BMMC_TILED_H(8, 256, 4),  BMMC_TILED_H(8, 512, 4),  BMMC_TILED_H(8, 256, 8), BMMC_TILED(8, 512, 8),
-    BMMC_TILED(8, 1024, 4),   BMMC_TILED(8, 256, 16),   BMMC_TILED(8, 256, 2),   BMMC_TILED(8, 512, 2),
-    BMMC_TILED_H(16, 256, 4), BMMC_TILED_H(16, 256, 8), BMMC_TILED(16, 512, 4),  BMMC_TILED(16, 256, 2),
-    BMMC_TILED(2, 256, 2),    BMMC_TILED(2, 256, 4),
-    BMMC_TILED(1, 256, 1),    BMMC_TILED(1, 256, 4),
+    BMMC_TILED_H(4, 256, 2),  BMMC_TILED_H(4, 1024, 2), BMMC_TILED_H(4, 1024, 4), BMMC_TILED_H(4, 256, 16),
+    BMMC_TILED_H(4, 512, 8),
+    BMMC_TILED_H(8, 256, 4),  BMMC_TILED_H(8, 512, 4),  BMMC_TILED_H(8, 256, 8), BMMC_TILED_H(8, 512, 8),
+    BMMC_TILED_H(8, 1024, 4), BMMC_TILED_H(8, 256, 16), BMMC_TILED_H(8, 256, 2), BMMC_TILED_H(8, 512, 2),
+    BMMC_TILED_H(16, 256, 4), BMMC_TILED_H(16, 256, 8), BMMC_TILED_H(16, 512, 4), BMMC_TILED_H(16, 256, 2),
+    BMMC_TILED_H(2, 256, 2),  BMMC_TILED_H(2, 256, 4),
+    BMMC_TILED_H(1, 256, 1),  BMMC_TILED_H(1, 256, 4),
 };
 #undef BMMC_TILED
 #undef BMMC_TILED_H

@@ -381,16 +381,20 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
         // One pass: the whole array fits a tile, A is tiled (its inputs that
         // reach the low b output bits are index bits), or the caller asked
         // for a general tile.
-        st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix);
+        // Auto: mixed tile selection for tiled matrices larger than a tile
+        // (their tiles' rows sit at power-of-two strides; mixing which tiles
+        // run together spreads the concurrent accesses).
+        const int mix = opt.tb_mix >= 0 ? opt.tb_mix : (n > D && opt.method != kMethodOnePass ? 1 : 0);
+        st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], mix);
         if (st != BMMC_OK) return st;
         p->npass = 1;
         return BMMC_OK;
     }
     BitMat T1, T2;
     if (!factorize_ulp(A, nullptr, nullptr, nullptr, &T1, &T2)) return BMMC_ERR_SINGULAR;
-    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix);
+    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0);
     if (st != BMMC_OK) return st;
-    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix);
+    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix > 0 ? 1 : 0);
     if (st != BMMC_OK) return st;
     p->npass = 2;
     return BMMC_OK;

@@ -51,7 +51,7 @@ struct PlanOptions {
     int a = 0;        // read-run bits; 0 = t
     int b = 0;        // write-run bits; 0 = t
     int swizzle = 1;  // 0: plain layout, 1: conflict-avoiding XOR layout
-    int tb_mix = 0;   // 1: tile-selecting vectors are XOR combinations of index bits
+    int tb_mix = -1;  // 1: tile-selecting vectors are XOR combinations of index bits; -1: auto
     KernelShape shape;
 };
 

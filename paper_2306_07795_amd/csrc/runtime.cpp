@@ -167,14 +167,34 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     p.shape = default_shape(w);
     if (!o) return p;
     p.method = o->method;
-    p.t = o->t;
-    p.a = o->run_in;
-    p.b = o->run_out;
+    if (o->method == BMMC_METHOD_ONEPASS && o->threads == 0 && o->iters == 0 && o->t == 0 &&
+        o->run_in == 0 && o->run_out == 0) {
+        // measured defaults for the general one-pass tile: a 2^13 tile with
+        // longer runs on one side
+        if (w == 4) { p.shape.iters = 8; p.a = 6; p.b = 7; }
+        if (w == 8) { p.shape.iters = 8; p.a = 7; p.b = 5; }
+    }
+    if (o->t) p.t = o->t;
+    if (o->run_in) p.a = o->run_in;
+    if (o->run_out) p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
-    p.tb_mix = (o->tile_order >> 1) & 1;
+    if (o->tile_order) p.tb_mix = (o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1);
     if (o->threads > 0) p.shape.nt = o->threads;
     if (o->iters > 0) p.shape.iters = o->iters;
     return p;
+}
+
+int resolve_hints(const bmmc_options_t* o, size_t bytes) {
+    const int h = o ? o->hints : 0;
+    if (h == 0) return bytes >= ((size_t)64 << 20) ? 3 : 0;
+    if (h & 4) return 0;
+    return h & 3;
+}
+
+int resolve_order(const bmmc_options_t* o) {
+    const int t = o ? o->tile_order : 0;
+    if (t == 0 || (t & 4)) return 0;
+    return t & 1;  // XCD-contiguous tiles; the mixing bit lives in the plan
 }
 
 // Name of the tiled kernel instance, shared by both passes of a plan.
@@ -368,7 +388,7 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     if (st != BMMC_OK) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
     return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, opts ? (uint32_t)opts->grid : 0,
-                        opts ? (opts->hints & 3) : 0, opts ? opts->tile_order : 0);
+                        resolve_hints(opts, bytes), resolve_order(opts));
 }
 
 int bmmc_permute(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
@@ -398,7 +418,8 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
 }
 
 int bmmc_copy(const void* in, void* out, size_t bytes, void* stream) {
-    return bmmc_copy_ex(in, out, bytes, 4, 0, stream);
+    const bool big = bytes >= ((size_t)64 << 20);
+    return bmmc_copy_ex(in, out, bytes, big ? 2 : 4, big ? 2 : 0, stream);
 }
 
 int bmmc_profile_begin(void) {

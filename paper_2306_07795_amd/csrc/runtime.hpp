@@ -71,6 +71,9 @@ struct LaunchScope {
 
 // Plan options from the public option struct.
 PlanOptions plan_options(const bmmc_options_t* o, int w);
+// Launch-time choices from the public option struct (zero = default).
+int resolve_hints(const bmmc_options_t* o, size_t bytes);
+int resolve_order(const bmmc_options_t* o);
 
 // Enqueue the passes of a plan (caller holds ds->mu).
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,

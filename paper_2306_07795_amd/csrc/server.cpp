@@ -4,7 +4,7 @@
 //  * submit() queues a request with its arrival time (the caller's clock is
 //    bmmc_server_now_ns; a future arrival time is honoured, so a client can
 //    hand over a whole open-loop schedule at once);
-//  * a planner thread plans requests as they arrive;
+//  * planner threads plan requests as they arrive;
 //  * the dispatcher admits planned requests in arrival order while their
 //    footprint (input + output + scratch) fits the budget, and whenever one
 //    of its K streams is free it launches every admitted request as one
@@ -135,7 +135,8 @@ struct Server {
     std::vector<Slot> slots;
     int64_t next_ticket = 1;
     bool stop = false;
-    std::thread planner, dispatcher;
+    std::vector<std::thread> planners;
+    std::thread dispatcher;
 
     // statistics
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0;
@@ -362,7 +363,9 @@ extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** hand
         hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     }
-    s->planner = std::thread([s] { s->plan_loop(); });
+    // Planning a random BMMC costs tens of microseconds; at tens of
+    // thousands of requests per second several planners keep up.
+    for (int k = 0; k < 4; k++) s->planners.emplace_back([s] { s->plan_loop(); });
     s->dispatcher = std::thread([s] { s->dispatch_loop(); });
     *handle_out = s;
     return BMMC_OK;
@@ -488,7 +491,7 @@ extern "C" int bmmc_server_destroy(void* handle) {
         s->stop = true;
         s->cv_work.notify_all();
     }
-    s->planner.join();
+    for (auto& t : s->planners) t.join();
     s->dispatcher.join();
     for (Slot& sl : s->slots) {
         hipStreamSynchronize(sl.stream);

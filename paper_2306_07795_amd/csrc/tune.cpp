@@ -40,8 +40,10 @@ int load_file(TuneCache& c, const char* path) {
         double ms;
         if (std::sscanf(line,
                         "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
-                        "\"iters\": %d, \"t\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %lf}",
-                        &n, &w, &method, &o.threads, &o.iters, &o.t, &o.grid, &o.swizzle, &ms) == 9) {
+                        "\"iters\": %d, \"t\": %d, \"run_in\": %d, \"run_out\": %d, \"hints\": %d, "
+                        "\"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %lf}",
+                        &n, &w, &method, &o.threads, &o.iters, &o.t, &o.run_in, &o.run_out, &o.hints,
+                        &o.tile_order, &o.grid, &o.swizzle, &ms) == 13) {
             o.method = method;
             c.plain[{n, w, method}] = {o, ms};
             count++;
@@ -76,9 +78,10 @@ int save_file(TuneCache& c, const char* path) {
         const bmmc_options_t& o = kv.second.first;
         std::fprintf(f,
                      "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
-                     "\"iters\": %d, \"t\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %.6f}\n",
+                     "\"iters\": %d, \"t\": %d, \"run_in\": %d, \"run_out\": %d, \"hints\": %d, "
+                     "\"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %.6f}\n",
                      std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), o.threads, o.iters,
-                     o.t, o.grid, o.swizzle, kv.second.second);
+                     o.t, o.run_in, o.run_out, o.hints, o.tile_order, o.grid, o.swizzle, kv.second.second);
     }
     for (auto& kv : c.batch) {
         const bmmc_batch_options_t& b = kv.second.first;
@@ -168,8 +171,8 @@ extern "C" int bmmc_tune_load(const char* path) {
     return load_file(c, path);
 }
 
-// Time every tile shape available for this width, two run widths and three
-// grid sizes on a random permutation of 2^n elements; keep the fastest.
+// Time tile shapes, run widths, cache hints, tile order and grid size on a
+// random permutation of 2^n elements; keep the fastest.
 extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, int reps,
                              bmmc_options_t* best_out, double* best_ms) {
     if (n < 1 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n out of range");
@@ -191,41 +194,52 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
     uint64_t rows[64], c;
     random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, rows, &c);
 
-    static const int kShapes[][2] = {{256, 2}, {256, 4}, {256, 8}, {256, 16}, {512, 2}, {512, 4},
-                                     {512, 8}, {1024, 2}, {1024, 4}, {256, 1}};
+    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 2}, {256, 2}};
     double best = 1e30;
     bmmc_options_t bo;
     std::memset(&bo, 0, sizeof(bo));
     Timer tm;
     for (auto& sh : kShapes) {
-        if (!tiled_kernel_available(elem_bytes, sh[0], sh[1])) continue;
+        if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
         KernelShape ks = default_shape(elem_bytes);
         ks.nt = sh[0];
         ks.iters = sh[1];
         const int D = ks.D();
-        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters);
-        for (int t = D / 2; t >= D / 2 - 1 && t >= ks.lv(); t--) {
-            for (int g = 0; g < 3; g++) {
-                bmmc_options_t o;
-                std::memset(&o, 0, sizeof(o));
-                o.method = method;
-                o.t = t;
-                o.threads = ks.nt;
-                o.iters = ks.iters;
-                o.swizzle = 1;
-                o.grid = g == 0 ? 0 : ds->cu_count * occ * g;
-                st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                if (st != BMMC_OK) continue;  // shape does not fit this size
-                hipEventRecord(tm.a, stream);
-                for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                hipEventRecord(tm.b, stream);
-                hipEventSynchronize(tm.b);
-                float ms = 0;
-                hipEventElapsedTime(&ms, tm.a, tm.b);
-                const double per = ms / reps;
-                if (per < best) {
-                    best = per;
-                    bo = o;
+        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters, 0);
+        const int h = D / 2;
+        // (read-run, write-run) bits: square, and one bit longer on either side
+        const int runs[][2] = {{h, h}, {D - h, h}, {h, D - h}, {h + 1, D - h - 1}, {D - h - 1, h + 1}};
+        for (auto& ab : runs) {
+            if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
+            for (int hints : {4, 2, 3}) {
+                for (int order : {4, 2}) {
+                    for (int g = 0; g < 2; g++) {
+                        bmmc_options_t o;
+                        std::memset(&o, 0, sizeof(o));
+                        o.method = method;
+                        o.t = ab[0] < ab[1] ? ab[0] : ab[1];
+                        o.run_in = ab[0];
+                        o.run_out = ab[1];
+                        o.threads = ks.nt;
+                        o.iters = ks.iters;
+                        o.swizzle = 1;
+                        o.hints = hints;
+                        o.tile_order = order;
+                        o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
+                        st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                        if (st != BMMC_OK) continue;  // shape does not fit this size
+                        hipEventRecord(tm.a, stream);
+                        for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                        hipEventRecord(tm.b, stream);
+                        hipEventSynchronize(tm.b);
+                        float ms = 0;
+                        hipEventElapsedTime(&ms, tm.a, tm.b);
+                        const double per = ms / reps;
+                        if (per < best) {
+                            best = per;
+                            bo = o;
+                        }
+                    }
                 }
             }
         }
