@@ -124,11 +124,12 @@ typedef struct {
 /* Knobs of the batched persistent kernel; zero means default / autotuned. */
 typedef struct {
     int workgroups;     /* persistent work-groups (default: fill every CU) */
-    int chunk_tiles;    /* tiles per work item */
-    int order;          /* 0 = largest arrays first, 1 = input order, 2 = interleaved */
-    int use_graph;      /* 1 (default): replay a captured hipGraph; -1: plain launch */
-    int method;         /* bmmc_method for the arrays that need two passes */
-    int reserved[3];
+    int chunk_tiles;    /* tiles per work item (default 4) */
+    int order;          /* 0 = largest arrays first, 1 = input order */
+    int use_graph;      /* 0 or 1 (default): replay a captured hipGraph; -1: plain launches */
+    int method;         /* bmmc_method for the arrays larger than a tile */
+    int hints;          /* as bmmc_options_t.hints (0: non-temporal above 64 MiB moved) */
+    int reserved[2];
 } bmmc_batch_options_t;
 
 /* Per-kernel timing gathered between bmmc_profile_begin and _end. */
@@ -224,9 +225,12 @@ int bmmc_copy(const void* in, void* out, size_t bytes, void* stream);
 int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, void* stream);
 
 /* Many independent permutations, each with its own n, width, A and c, in one
-   persistent kernel launch replayed from a captured hipGraph.  Arrays that fit
-   one tile take one pass; the others take the paper's two tiled passes, the
-   second pass of an array starting once its first pass is complete.  descs is
+   replay of a captured hipGraph holding two launches of a persistent kernel:
+   the first runs every one-pass array (those that fit one tile, or are tiled)
+   and the first passes of the others (the paper's two tiled passes), the
+   second runs those second passes.  Arrays of 1- or 2-byte elements, or too
+   small for one 16-byte vector, go through the single-array kernels on the
+   same stream.  descs is
    a host array of `count` descriptors; every in/out pair obeys the rules
    above and no out may overlap another array's in or out.  Scratch, the
    device descriptor table and the graph are owned by the library.
@@ -234,12 +238,6 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
 int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream);
 int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count,
                             const bmmc_batch_options_t* opts, void* stream);
-
-/* Wait for `stream` and report in *timed_out whether the last batched launch
-   on it gave up waiting for a first pass (1) or not (0).  The persistent
-   kernel bounds every wait instead of hanging; a timeout means its output is
-   incomplete.  Errors: _HIP. */
-int bmmc_batched_status(void* stream, int* timed_out);
 
 /* ------------------------------------------------------------- autotuner */
 

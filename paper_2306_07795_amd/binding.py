@@ -53,7 +53,7 @@ class Desc(_c.Structure):
 
 class BatchOptions(_c.Structure):
     _fields_ = [("workgroups", _i32), ("chunk_tiles", _i32), ("order", _i32),
-                ("use_graph", _i32), ("method", _i32), ("reserved", _i32 * 3)]
+                ("use_graph", _i32), ("method", _i32), ("hints", _i32), ("reserved", _i32 * 2)]
 
 
 class KernelStat(_c.Structure):
@@ -110,7 +110,6 @@ def lib():
         "bmmc_copy_ex": (_i32, [_vp, _vp, _c.c_size_t, _i32, _i32, _vp]),
         "bmmc_permute_batched": (_i32, [P(Desc), _i32, _vp]),
         "bmmc_permute_batched_ex": (_i32, [P(Desc), _i32, P(BatchOptions), _vp]),
-        "bmmc_batched_status": (_i32, [_vp, P(_i32)]),
         "bmmc_profile_begin": (_i32, []),
         "bmmc_profile_end": (_i32, [P(KernelStat), _i32]),
         "bmmc_autotune_batched": (_i32, [P(Desc), _i32, _vp, _i32, P(BatchOptions), P(_dbl)]),
@@ -138,7 +137,7 @@ def exported_names():
     return [
         "bmmc_strerror", "bmmc_last_error", "bmmc_version", "bmmc_is_tiled", "bmmc_factorize",
         "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
-        "bmmc_copy", "bmmc_copy_ex", "bmmc_permute_batched", "bmmc_permute_batched_ex", "bmmc_batched_status",
+        "bmmc_copy", "bmmc_copy_ex", "bmmc_permute_batched", "bmmc_permute_batched_ex",
         "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
@@ -304,13 +303,6 @@ def bmmc_permute_batched(items, stream=None, opts=None):
     else:
         _check(lib().bmmc_permute_batched_ex(arr, count, _batch_options(opts), _stream(stream)))
     del keep
-
-
-def bmmc_batched_status(stream=None) -> bool:
-    """Synchronizes the stream; True if the last batched launch gave up a wait."""
-    flag = _i32(0)
-    _check(lib().bmmc_batched_status(_stream(stream), _c.byref(flag)))
-    return bool(flag.value)
 
 
 def bmmc_profile_begin():

@@ -1,12 +1,14 @@
 // Batched form: many arrays, each with its own n, width, A and c, in one
-// launch of the persistent kernel, replayed from a captured hipGraph.
+// replay of a captured hipGraph.
 //
 // The host plans every array (plan cache), lays the passes and the work items
-// out in a pinned staging buffer, copies them to a device-resident table and
-// launches the graph [clear counters] -> [persistent kernel].  The graph's
-// kernel arguments are fixed device pointers (the item count lives in the
-// table), so one instantiated graph serves every call on a stream until the
-// table has to grow.
+// out in a pinned staging buffer and copies them to a device-resident table.
+// The graph is [clear heads] -> [persistent kernel, phase 0] -> [persistent
+// kernel, phase 1]: phase 0 runs the one-pass arrays and the first passes of
+// the two-pass arrays, phase 1 their second passes.  The graph's kernel
+// arguments are fixed device pointers (the item ranges live in the table), so
+// one instantiated graph serves every call on a stream until the table has to
+// grow.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -20,15 +22,14 @@ namespace {
 
 struct BatchState {
     hipStream_t stream = nullptr;
-    // device table: [header (nitems, pad) | passes | items | counters+head+status]
+    // device table: [range[3] | passes | items | heads[2]]
     void* dev = nullptr;
-    size_t dev_bytes = 0;
     void* host = nullptr;  // pinned staging of the same layout
-    size_t cap_passes = 0, cap_items = 0, cap_counters = 0;
+    size_t cap_passes = 0, cap_items = 0;
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
     hipGraphExec_t exec = nullptr;
     uint32_t exec_grid = 0;
-    uint32_t exec_spin = 0;
+    int exec_hints = -1;
 };
 
 struct BatchRegistry {
@@ -45,24 +46,23 @@ BatchRegistry& registry() {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t passes_off, items_off, counters_off, total;
+    size_t passes_off, items_off, heads_off, total;
 };
 
-Layout layout_for(size_t np, size_t ni, size_t nc) {
+Layout layout_for(size_t np, size_t ni) {
     Layout L;
     L.passes_off = 256;
     L.items_off = align_up(L.passes_off + np * sizeof(BatchPass), 256);
-    L.counters_off = align_up(L.items_off + ni * sizeof(BatchItem), 256);
-    L.total = align_up(L.counters_off + (nc + 2) * sizeof(uint32_t), 256);
+    L.heads_off = align_up(L.items_off + ni * sizeof(BatchItem), 256);
+    L.total = L.heads_off + 256;
     return L;
 }
 
-int ensure_capacity(BatchState* bs, size_t np, size_t ni, size_t nc) {
-    if (np <= bs->cap_passes && ni <= bs->cap_items && nc <= bs->cap_counters) return BMMC_OK;
+int ensure_capacity(BatchState* bs, size_t np, size_t ni) {
+    if (np <= bs->cap_passes && ni <= bs->cap_items) return BMMC_OK;
     np = std::max(np * 2, bs->cap_passes);
     ni = std::max(ni * 2, bs->cap_items);
-    nc = std::max(nc * 2, bs->cap_counters);
-    Layout L = layout_for(np, ni, nc);
+    Layout L = layout_for(np, ni);
     hipError_t e;
     if (bs->dev) {
         e = hipStreamSynchronize(bs->stream);
@@ -87,10 +87,8 @@ int ensure_capacity(BatchState* bs, size_t np, size_t ni, size_t nc) {
         bs->host = nullptr;
         return set_error(BMMC_ERR_NOMEM, "pinned staging of %zu bytes: %s", L.total, hipGetErrorString(e));
     }
-    bs->dev_bytes = L.total;
     bs->cap_passes = np;
     bs->cap_items = ni;
-    bs->cap_counters = nc;
     return BMMC_OK;
 }
 
@@ -106,15 +104,26 @@ BatchState* batch_state(hipStream_t stream, int device) {
     return bs;
 }
 
-// Capture [zero counters] -> [persistent kernel] into a graph for this state.
-int build_graph(BatchState* bs, uint32_t grid, uint32_t spin) {
-    if (bs->exec && bs->exec_grid == grid && bs->exec_spin == spin) return BMMC_OK;
+// Enqueue [clear heads] -> phase 0 -> phase 1 on `s` (captured or not).
+hipError_t enqueue_phases(BatchState* bs, uint32_t grid, int hints, hipStream_t s) {
+    Layout L = layout_for(bs->cap_passes, bs->cap_items);
+    uint8_t* d = (uint8_t*)bs->dev;
+    uint32_t* heads = (uint32_t*)(d + L.heads_off);
+    const BatchPass* passes = (const BatchPass*)(d + L.passes_off);
+    const BatchItem* items = (const BatchItem*)(d + L.items_off);
+    const uint32_t* range = (const uint32_t*)d;
+    hipError_t e = launch_zero(heads, 2, s);
+    if (e == hipSuccess) e = launch_batched(passes, items, range, 0, heads, grid, hints, s);
+    if (e == hipSuccess) e = launch_batched(passes, items, range, 1, heads + 1, grid, hints, s);
+    return e;
+}
+
+int build_graph(BatchState* bs, uint32_t grid, int hints) {
+    if (bs->exec && bs->exec_grid == grid && bs->exec_hints == hints) return BMMC_OK;
     if (bs->exec) {
         hipGraphExecDestroy(bs->exec);
         bs->exec = nullptr;
     }
-    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
-    uint8_t* d = (uint8_t*)bs->dev;
     hipStream_t cap;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -123,11 +132,7 @@ int build_graph(BatchState* bs, uint32_t grid, uint32_t spin) {
         hipStreamDestroy(cap);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    uint32_t* counters = (uint32_t*)(d + L.counters_off);
-    launch_zero(counters, (uint32_t)bs->cap_counters + 2, cap);
-    launch_batched((const BatchPass*)(d + L.passes_off), (const BatchItem*)(d + L.items_off),
-                   (const uint32_t*)d, counters, counters + bs->cap_counters,
-                   counters + bs->cap_counters + 1, grid, spin, cap);
+    enqueue_phases(bs, grid, hints, cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
     hipStreamDestroy(cap);
@@ -139,7 +144,7 @@ int build_graph(BatchState* bs, uint32_t grid, uint32_t spin) {
         return hip_fail(e, "hipGraphInstantiate");
     }
     bs->exec_grid = grid;
-    bs->exec_spin = spin;
+    bs->exec_hints = hints;
     return BMMC_OK;
 }
 
@@ -215,6 +220,7 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
     int st;
     std::vector<size_t> work;
+    double moved = 0;
     for (size_t i = 0; i < arrays.size(); i++) {
         if (arrays[i].single) {
             st = enqueue_plan(ds, *arrays[i].plan, arrays[i].in, arrays[i].out, stream, 0);
@@ -223,46 +229,38 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
             if (arrays[i].plan->npass == 2 && !arrays[i].scratch)
                 return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");
             work.push_back(i);
+            moved += 2.0 * (double)arrays[i].bytes;
         }
     }
     if (work.empty()) return BMMC_OK;
 
-    // Queue order.  0: two-pass arrays largest first, then one-pass arrays,
-    // then the second passes; 1: input order; 2: as 0, but the second pass
-    // of each array is queued a few arrays after its first pass, while its
-    // scratch is still warm in the last-level cache.
-    if (o.order == 0 || o.order == 2)
-        std::stable_sort(work.begin(), work.end(), [&](size_t x, size_t y) {
-            const bool px = arrays[x].plan->npass == 2, py = arrays[y].plan->npass == 2;
-            if (px != py) return px;
-            return arrays[x].bytes > arrays[y].bytes;
-        });
+    // Queue order inside each phase.  0: largest arrays first (the short
+    // items at the end even out the finish); 1: input order.
+    if (o.order != 1)
+        std::stable_sort(work.begin(), work.end(),
+                         [&](size_t x, size_t y) { return arrays[x].bytes > arrays[y].bytes; });
 
-    size_t npasses = 0, ncounters = 0, nitems = 0;
+    size_t npasses = 0, nitems = 0;
     for (size_t a : work) {
         const Plan& p = *arrays[a].plan;
         npasses += p.npass;
-        if (p.npass == 2) ncounters++;
         for (int k = 0; k < p.npass; k++) nitems += ((1u << p.pass[k].tab.ntb) + chunk - 1) / chunk;
     }
     BatchState* bs = batch_state(stream, ds->device);
-    st = ensure_capacity(bs, npasses, nitems, ncounters);
+    st = ensure_capacity(bs, npasses, nitems);
     if (st != BMMC_OK) return st;
     if (bs->staged) {
         hipError_t e = hipEventSynchronize(bs->staged);  // staging buffer free again
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     }
-    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
+    Layout L = layout_for(bs->cap_passes, bs->cap_items);
     uint8_t* h = (uint8_t*)bs->host;
     BatchPass* hp = (BatchPass*)(h + L.passes_off);
     BatchItem* hi = (BatchItem*)(h + L.items_off);
 
     // Pass table.
     uint32_t pidx = 0;
-    int32_t counter = 0;
     std::vector<uint32_t> first_pass(arrays.size(), 0);
-    std::vector<int32_t> counter_of(arrays.size(), -1);
-    double moved = 0;
     for (size_t a : work) {
         const BatchArray& ba = arrays[a];
         const Plan& p = *ba.plan;
@@ -275,10 +273,8 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
             bp.w = (uint32_t)p.w;
             bp.tab = p.pass[k].tab;
         }
-        if (p.npass == 2) counter_of[a] = counter++;
-        moved += 2.0 * (double)ba.bytes;
     }
-    // Work items: ranges of `chunk` tiles.
+    // Work items, phase 0 then phase 1, each a range of `chunk` tiles.
     size_t ni = 0;
     auto emit = [&](size_t a, int k) {
         const Plan& p = *arrays[a].plan;
@@ -289,36 +285,16 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
             it.pass = first_pass[a] + (uint32_t)k;
             it.tile_begin = t0;
             it.tile_end = std::min(ntiles, t0 + chunk);
-            it.wait_on = -1;
-            it.signal = -1;
-            if (p.npass == 2) {
-                if (k == 0) {
-                    it.signal = counter_of[a];
-                } else {
-                    it.wait_on = counter_of[a];
-                    it.wait_count = 1u << p.pass[0].tab.ntb;
-                }
-            }
         }
     };
-    if (o.order == 2) {
-        const size_t lag = 4;
-        std::vector<size_t> pending;
-        for (size_t a : work) {
-            emit(a, 0);
-            if (arrays[a].plan->npass == 2) pending.push_back(a);
-            if (pending.size() > lag) {
-                emit(pending.front(), 1);
-                pending.erase(pending.begin());
-            }
-        }
-        for (size_t a : pending) emit(a, 1);
-    } else {
-        for (size_t a : work) emit(a, 0);
-        for (size_t a : work)
-            if (arrays[a].plan->npass == 2) emit(a, 1);
-    }
-    *(uint32_t*)h = (uint32_t)ni;
+    for (size_t a : work) emit(a, 0);
+    const uint32_t phase0_end = (uint32_t)ni;
+    for (size_t a : work)
+        if (arrays[a].plan->npass == 2) emit(a, 1);
+    uint32_t* range = (uint32_t*)h;
+    range[0] = 0;
+    range[1] = phase0_end;
+    range[2] = (uint32_t)ni;
 
     // Upload only what is used, then launch.
     hipError_t e = hipMemcpyAsync(bs->dev, bs->host, L.passes_off + pidx * sizeof(BatchPass),
@@ -332,38 +308,19 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
 
     const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
                                            : (uint32_t)(ds->cu_count * batched_occupancy());
-    const uint32_t spin = 1u << 26;  // each spin sleeps: a bound of about a minute
+    // Non-temporal accesses pay off once the data outgrows the last-level cache.
+    const int hints = o.hints > 0 ? ((o.hints & 4) ? 0 : (o.hints & 3))
+                                  : (moved >= 2.0 * (double)((size_t)64 << 20) ? 3 : 0);
     LaunchScope ls(ds, stream, "k_batched", moved);
     if (o.use_graph >= 0) {
-        st = build_graph(bs, grid, spin);
+        st = build_graph(bs, grid, hints);
         if (st != BMMC_OK) return st;
         e = hipGraphLaunch(bs->exec, stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        uint8_t* d = (uint8_t*)bs->dev;
-        uint32_t* counters = (uint32_t*)(d + L.counters_off);
-        e = launch_zero(counters, (uint32_t)bs->cap_counters + 2, stream);
-        if (e == hipSuccess)
-            e = launch_batched((const BatchPass*)(d + L.passes_off), (const BatchItem*)(d + L.items_off),
-                               (const uint32_t*)d, counters, counters + bs->cap_counters,
-                               counters + bs->cap_counters + 1, grid, spin, stream);
+        e = enqueue_phases(bs, grid, hints, stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
-    return BMMC_OK;
-}
-
-int read_batched_status(DeviceState* ds, hipStream_t stream, int* timed_out) {
-    BatchState* bs = batch_state(stream, ds->device);
-    if (timed_out) *timed_out = 0;
-    if (!bs->dev) return BMMC_OK;
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    Layout L = layout_for(bs->cap_passes, bs->cap_items, bs->cap_counters);
-    uint32_t v = 0;
-    e = hipMemcpy(&v, (uint8_t*)bs->dev + L.counters_off + (bs->cap_counters + 1) * sizeof(uint32_t),
-                  sizeof(v), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch status)");
-    if (timed_out) *timed_out = v ? 1 : 0;
     return BMMC_OK;
 }
 
@@ -425,13 +382,4 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
 
 extern "C" int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream) {
     return bmmc_permute_batched_ex(descs, count, nullptr, stream);
-}
-
-// Wait for the stream and report whether the last batched launch on it had to
-// give up a wait (1) or not (0).
-extern "C" int bmmc_batched_status(void* stream, int* timed_out) {
-    int st;
-    DeviceState* ds = device_state(&st);
-    if (!ds) return st;
-    return read_batched_status(ds, (hipStream_t)stream, timed_out);
 }

@@ -332,92 +332,68 @@ hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream) {
 
 // ---------------------------------------------------------------------------
 // Batched persistent kernel.  Work items are ranges of tiles of one pass of
-// one array, taken in queue order through an atomic head.  A second-pass item
-// waits until its array's first pass has signalled all its tiles; since every
-// first-pass item of that array sits earlier in the queue, it was taken by a
-// running work-group that never waits, so the wait ends.  The wait is also
-// bounded by spin_limit: past it the kernel records an error in status[0] and
-// skips the item instead of hanging.  Every width (4, 8 or 16 bytes; the host
-// sends narrower elements through the single-array kernels) uses the same
-// 16 KiB tile buffer: 256 threads x 4 vectors x 16 bytes.
+// one array, taken in queue order through an atomic head.  One launch runs
+// one phase: the first passes of two-pass arrays together with the one-pass
+// arrays, then a second launch (stream-ordered, in the same graph) runs the
+// second passes, so every second pass reads a scratch array whose first pass
+// has completed, without any wait or device-wide fence inside a kernel.
+// Every width (4, 8 or 16 bytes; the host sends narrower elements through
+// the single-array kernels) uses the same 16 KiB tile buffer: 256 threads x
+// 4 vectors x 16 bytes.
 // ---------------------------------------------------------------------------
 constexpr int kBatchNT = 256;
 constexpr int kBatchIters = 4;
 
-template <int W>
+template <int W, int HINT>
 __device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, uint32_t t1,
                                             uint8_t* lds_bytes, uint32_t tid) {
-    using C = TileCtx<W, kBatchNT, kBatchIters>;
+    using C = TileCtx<W, kBatchNT, kBatchIters, HINT>;
     C ctx;
     ctx.init(bp.tab, tid);
     for (uint32_t tile = t0; tile < t1; tile++)
         ctx.run(bp.tab, (const u32x4*)bp.in, (u32x4*)bp.out, (typename C::E*)lds_bytes, tile, tid);
 }
 
+// range[phase] .. range[phase + 1] are this launch's items.
+template <int HINT>
 __global__ void __launch_bounds__(kBatchNT)
 k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ items,
-          const uint32_t* __restrict__ nitems_ptr, uint32_t* counters, uint32_t* head, uint32_t* status,
-          uint32_t spin_limit) {
-    const uint32_t nitems = *nitems_ptr;
+          const uint32_t* __restrict__ range, uint32_t phase, uint32_t* head) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchNT * kBatchIters * 16];
-    __shared__ uint32_t s_item, s_ok;
+    __shared__ uint32_t s_item;
     const uint32_t tid = threadIdx.x;
+    const uint32_t first = range[phase], last = range[phase + 1];
     for (;;) {
         if (tid == 0)
-            s_item = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_item = first + __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const uint32_t idx = s_item;
-        if (idx >= nitems) break;
+        __syncthreads();  // every thread has read s_item before it is rewritten
+        if (idx >= last) break;
         const BatchItem item = items[idx];
-        if (item.wait_on >= 0) {
-            if (tid == 0) {
-                uint32_t spins = 0, ok = 1;
-                while (__hip_atomic_load(&counters[item.wait_on], __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT) < item.wait_count) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > spin_limit) {
-                        ok = 0;
-                        __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                }
-                s_ok = ok;
-            }
-            __syncthreads();
-            if (!s_ok) {
-                __syncthreads();
-                continue;
-            }
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);  // see the first pass's stores
-        }
         const BatchPass& bp = passes[item.pass];
         switch (bp.w) {
-            case 4: batch_tiles<4>(bp, item.tile_begin, item.tile_end, lds, tid); break;
-            case 8: batch_tiles<8>(bp, item.tile_begin, item.tile_end, lds, tid); break;
-            default: batch_tiles<16>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 4: batch_tiles<4, HINT>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 8: batch_tiles<8, HINT>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            default: batch_tiles<16, HINT>(bp, item.tile_begin, item.tile_end, lds, tid); break;
         }
-        if (item.signal >= 0) {
-            __threadfence();  // publish this thread's stores device-wide
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_fetch_add(&counters[item.signal], item.tile_end - item.tile_begin,
-                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();  // s_item is rewritten next round
     }
 }
 
-hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* nitems,
-                          uint32_t* counters, uint32_t* head, uint32_t* status, uint32_t grid,
-                          uint32_t spin_limit, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, nitems,
-                       counters, head, status, spin_limit);
+hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* range,
+                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, hipStream_t stream) {
+    switch (hints & 3) {
+        case 0: hipLaunchKernelGGL(k_batched<0>, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, range, phase, head); break;
+        case 1: hipLaunchKernelGGL(k_batched<1>, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, range, phase, head); break;
+        case 2: hipLaunchKernelGGL(k_batched<2>, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, range, phase, head); break;
+        default: hipLaunchKernelGGL(k_batched<3>, dim3(grid), dim3(kBatchNT), 0, stream, passes, items, range, phase, head); break;
+    }
     return hipGetLastError();
 }
 
 int batched_occupancy() {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched, kBatchNT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0>, kBatchNT, 0) != hipSuccess)
         blocks = 4;
     return blocks > 0 ? blocks : 1;
 }

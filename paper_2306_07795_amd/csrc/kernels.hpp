@@ -37,13 +37,10 @@ hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt = 4,
                        int hints = 0);
 
-// Batched persistent kernel (batched.hip).
-// passes / items / nitems / counters / head are device pointers; counters and
-// head must be zero at launch.  status[0] receives a nonzero code if a wait
-// timed out (the kernel then skips the item rather than hang).
-hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* nitems,
-                          uint32_t* counters, uint32_t* head, uint32_t* status,
-                          uint32_t grid, uint32_t spin_limit, hipStream_t stream);
+// Batched persistent kernel: runs items range[phase] .. range[phase + 1]
+// (device pointers; *head must be zero at launch).
+hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* range,
+                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, hipStream_t stream);
 // Resident work-groups per CU of the batched kernel / of a tiled kernel.
 int batched_occupancy();
 int tiled_occupancy(int w, int nt, int iters, int hints = 0);

@@ -46,10 +46,7 @@ struct BatchItem {
     uint32_t pass;        // index into the pass table
     uint32_t tile_begin;  // first tile
     uint32_t tile_end;    // one past the last tile
-    int32_t wait_on;      // counter that must reach wait_count first, or -1
-    uint32_t wait_count;
-    int32_t signal;       // counter bumped by (tile_end - tile_begin) when done, or -1
-    uint32_t pad_[2];
+    uint32_t pad_;
 };
 
 // Per-pass device descriptor for the batched kernel.

@@ -96,7 +96,6 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArr
 // Enqueue one batched launch (caller holds ds->mu).
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream);
-int read_batched_status(DeviceState* ds, hipStream_t stream, int* timed_out);
 uint64_t batch_signature(const bmmc_desc_t* descs, int count);
 
 // Tuning cache lookups (tune.cpp); false when nothing is cached.

@@ -278,7 +278,7 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     std::memset(&bo, 0, sizeof(bo));
     Timer tm;
     for (int chunk : kChunks) {
-        for (int order = 0; order < 3; order++) {
+        for (int order = 0; order < 2; order++) {
             for (int g = 1; g <= 2; g++) {
                 bmmc_batch_options_t o;
                 std::memset(&o, 0, sizeof(o));
