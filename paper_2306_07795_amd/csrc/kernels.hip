@@ -90,20 +90,20 @@ struct TileCtx {
         vlim = 1u << (P.d - LV);
     }
 
-    __device__ __forceinline__ void run(const PassTables& P, const u32x4* __restrict__ in,
-                                        u32x4* __restrict__ out, E* lds, uint32_t tile,
-                                        uint32_t tid) const {
-        // Per-tile part: coset representative r, output base, LDS offset.
-        uint32_t r = 0, yb = P.c_hi, gx = P.c_lds;
+    // Coset representative of a tile: XOR of the tile-selecting vectors of
+    // its set bits (uniform over the work-group: scalar work).
+    __device__ __forceinline__ uint32_t tile_in(const PassTables& P, uint32_t tile) const {
+        uint32_t r = 0;
 #pragma unroll
-        for (int j = 0; j < kMaxTbBits; j++) {
-            if (j < (int)P.ntb && ((tile >> j) & 1u)) {
-                r ^= P.tb_in[j];
-                yb ^= P.tb_out[j];
-                gx ^= P.tb_lds[j];
-            }
-        }
-        Vec16<W> buf[ITERS];
+        for (int j = 0; j < kMaxTbBits; j++)
+            if (j < (int)P.ntb && ((tile >> j) & 1u)) r ^= P.tb_in[j];
+        return r;
+    }
+
+    // Read phase, global part: ITERS 16-byte loads, each inside one input run.
+    __device__ __forceinline__ void load(const PassTables& P, const u32x4* __restrict__ in, uint32_t tile,
+                                         uint32_t tid, Vec16<W>* buf) const {
+        const uint32_t r = tile_in(P, tile);
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
@@ -111,6 +111,10 @@ struct TileCtx {
                 buf[it].v = ld16<HINT>(in + (x >> LV));
             }
         }
+    }
+
+    // Read phase, LDS part: each element to its swizzled slot F(v).
+    __device__ __forceinline__ void to_lds(const PassTables& P, E* lds, uint32_t tid, const Vec16<W>* buf) const {
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
@@ -119,7 +123,20 @@ struct TileCtx {
                 for (int e = 0; e < VEC; e++) lds[f ^ lin_const<0, LV>(P.F, e)] = buf[it].e[e];
             }
         }
-        __syncthreads();
+    }
+
+    // Write phase: gather each output vector from slots G(u), store it to
+    // one output run at T.r XOR c XOR Y(u).
+    __device__ __forceinline__ void store(const PassTables& P, u32x4* __restrict__ out, const E* lds,
+                                          uint32_t tile, uint32_t tid) const {
+        uint32_t yb = P.c_hi, gx = P.c_lds;
+#pragma unroll
+        for (int j = 0; j < kMaxTbBits; j++) {
+            if (j < (int)P.ntb && ((tile >> j) & 1u)) {
+                yb ^= P.tb_out[j];
+                gx ^= P.tb_lds[j];
+            }
+        }
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
@@ -131,7 +148,29 @@ struct TileCtx {
                 st16<HINT>(out + (y >> LV), o.v);
             }
         }
-        __syncthreads();
+    }
+
+    // Tiles first, first + step, ... below last.  The loads of the next tile
+    // are issued right after the barrier that ends the current tile's LDS
+    // writes, so they are in flight while the current tile is written out.
+    __device__ __forceinline__ void run_tiles(const PassTables& P, const u32x4* __restrict__ in,
+                                              u32x4* __restrict__ out, E* lds, uint32_t first,
+                                              uint32_t last, uint32_t step, uint32_t tid) const {
+        if (first >= last) return;
+        Vec16<W> buf[ITERS];
+        uint32_t tile = first;
+        load(P, in, tile, tid, buf);
+        for (;;) {
+            to_lds(P, lds, tid, buf);
+            __syncthreads();
+            const uint32_t next = tile + step;
+            const bool more = next < last;
+            if (more) load(P, in, next, tid, buf);
+            store(P, out, lds, tile, tid);
+            __syncthreads();
+            if (!more) break;
+            tile = next;
+        }
     }
 };
 
@@ -155,8 +194,7 @@ k_tiled(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables 
     __shared__ typename C::E lds[1 << C::D];
     C ctx;
     ctx.init(P, threadIdx.x);
-    for (uint32_t tile = logical_block(xcds); tile < ntiles; tile += gridDim.x)
-        ctx.run(P, in, out, lds, tile, threadIdx.x);
+    ctx.run_tiles(P, in, out, lds, logical_block(xcds), ntiles, gridDim.x, threadIdx.x);
 }
 
 struct TiledEntry {
@@ -350,8 +388,7 @@ __device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, ui
     using C = TileCtx<W, kBatchNT, kBatchIters, HINT>;
     C ctx;
     ctx.init(bp.tab, tid);
-    for (uint32_t tile = t0; tile < t1; tile++)
-        ctx.run(bp.tab, (const u32x4*)bp.in, (u32x4*)bp.out, (typename C::E*)lds_bytes, tile, tid);
+    ctx.run_tiles(bp.tab, (const u32x4*)bp.in, (u32x4*)bp.out, (typename C::E*)lds_bytes, t0, t1, 1, tid);
 }
 
 // range[phase] .. range[phase + 1] are this launch's items.
