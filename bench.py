@@ -100,6 +100,44 @@ def cpu_baseline(a, n, rows, c, budget_s=12.0):
             "sample": f"the full workload (2^{n} elements), {reps} repetition(s), {dt:.2f} s each"}
 
 
+def kernel_key(name):
+    """'void bmmc::k_tiled<4, 256, 4, 3>(...)' -> 'k_tiled<4,256,4,3>'."""
+    base = name.split("(")[0].replace("void ", "").replace("bmmc::", "")
+    return base.replace(" ", "")
+
+
+def write_traffic(fetch_dir, write_dir, nbytes):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of this benchmark
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled
+    by the ratio (algorithmic bytes / counter bytes) it shows for the plain
+    copy kernel k_copy<4,0>, which reads and writes `nbytes` per launch."""
+    import csv
+    import glob
+    import statistics
+
+    def means(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    out.setdefault(kernel_key(r["Kernel_Name"]), []).append(float(r["Counter_Value"]) * 1024.0)
+        return {k: statistics.mean(v) for k, v in out.items()}
+
+    fetch, write = means(fetch_dir, "FETCH_SIZE"), means(write_dir, "WRITE_SIZE")
+    f_scale = nbytes / fetch["k_copy<4,0>"]
+    w_scale = nbytes / write["k_copy<4,0>"]
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        rb, wb = fetch[k] * f_scale, write[k] * w_scale
+        kernels[k] = {"read_bytes_per_launch": round(rb), "write_bytes_per_launch": round(wb),
+                      "bytes_per_launch": round(rb + wb)}
+    rec = {"kernel_source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "calibration": "k_copy<4,0> moving %d bytes each way" % nbytes, "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def traffic_for(kernel):
     """HBM bytes per launch measured with rocprofv3 counters, if they were taken
     on the current kernel source (else None)."""
@@ -230,7 +268,14 @@ def main():
     ap.add_argument("--served-rate", type=float, default=20000.0)
     ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--extras-out", default=None, help="write extra measurements (JSON) here")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of this "
+                         "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        n, w = WORKLOADS[args.workload][:2]
+        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w), indent=1))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -296,6 +341,8 @@ def main():
 
     # bounds in the same session
     copy_ms, copy_how = best_device_copy(x, y, nbytes, stream)
+    # the traffic calibration kernel, k_copy<4,0>, launched at least once
+    B.bmmc_copy_ex(x, y, nbytes, 4, 0, stream)
     dev_copy = gbps(nbytes, copy_ms)
     extras = {"device_copy": copy_how}
     if method == B.METHOD_AUTO:

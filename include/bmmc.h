@@ -88,7 +88,8 @@ typedef struct {
     /* 1: give each XCD a contiguous range of tiles (work-groups are dealt
        to the XCDs round-robin); 2: select tiles through XOR-combined index
        bits; 3: both; 4: neither; 0: 2 for one-pass plans of tiled matrices
-       larger than a tile, 4 otherwise. */
+       larger than a tile, 4 otherwise.  Adding 8 also fills the tile with
+       XOR-combined iteration bits instead of the lowest free index bits. */
     int tile_order;
     int reserved[2];
 } bmmc_options_t;

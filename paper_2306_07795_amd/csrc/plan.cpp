@@ -148,7 +148,7 @@ KernelShape default_shape(int w) {
 int default_t(const KernelShape& ks) { return ks.D() / 2; }
 
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
-               uint64_t seed, PassPlan* p, int tb_mix) {
+               uint64_t seed, PassPlan* p, int tb_mix, int iter_mix) {
     const int n = T.n;
     const int D = ks.D();
     BitMat Ti;
@@ -206,11 +206,20 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
         p->dim_v0 = d;
         if (d > D) return BMMC_ERR_RANGE;
         // Iteration bits: the lowest remaining index bits fill the tile.
+        // With iter_mix each is XOR-ed with a random choice of the remaining
+        // higher index bits, so one tile's rows spread over the address space.
+        uint64_t s = seed ^ 0x17E7ull;
         for (int j = a; j < n && d < D; j++) {
             if (!vb.contains(1ull << j)) {
-                vb.insert(1ull << j);
-                X[d++] = 1ull << j;
-                p->iter_mask |= 1ull << j;
+                uint64_t v = 1ull << j;
+                if (iter_mix) {
+                    s = mix64(s);
+                    for (int k = j + 1; k < n; k++)
+                        if (((s >> (k & 63)) & 1ull) && !vb.contains(1ull << k)) v ^= 1ull << k;
+                }
+                if (!vb.insert(v)) continue;
+                X[d++] = v;
+                p->iter_mask |= v;
             }
         }
     }
@@ -385,16 +394,16 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
         // (their tiles' rows sit at power-of-two strides; mixing which tiles
         // run together spreads the concurrent accesses).
         const int mix = opt.tb_mix >= 0 ? opt.tb_mix : (n > D && opt.method != kMethodOnePass ? 1 : 0);
-        st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], mix);
+        st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], mix, opt.iter_mix);
         if (st != BMMC_OK) return st;
         p->npass = 1;
         return BMMC_OK;
     }
     BitMat T1, T2;
     if (!factorize_ulp(A, nullptr, nullptr, nullptr, &T1, &T2)) return BMMC_ERR_SINGULAR;
-    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0);
+    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0, opt.iter_mix);
     if (st != BMMC_OK) return st;
-    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix > 0 ? 1 : 0);
+    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix > 0 ? 1 : 0, opt.iter_mix);
     if (st != BMMC_OK) return st;
     p->npass = 2;
     return BMMC_OK;

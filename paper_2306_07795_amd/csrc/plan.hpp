@@ -52,6 +52,7 @@ struct PlanOptions {
     int b = 0;        // write-run bits; 0 = t
     int swizzle = 1;  // 0: plain layout, 1: conflict-avoiding XOR layout
     int tb_mix = -1;  // 1: tile-selecting vectors are XOR combinations of index bits; -1: auto
+    int iter_mix = 0; // 1: iteration vectors are XOR combinations of index bits
     KernelShape shape;
 };
 
@@ -79,7 +80,7 @@ bool factorize_ulp(const BitMat& A, BitMat* U, BitMat* L, BitMat* P, BitMat* T1,
 // 2^a and write runs of 2^b elements, for the given kernel shape.
 // Returns 0 or a negative bmmc_status.
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
-               uint64_t seed, PassPlan* out, int tb_mix = 0);
+               uint64_t seed, PassPlan* out, int tb_mix = 0, int iter_mix = 0);
 
 // Full plan for out[A.x XOR c] = in[x].
 int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions& opt, Plan* out);

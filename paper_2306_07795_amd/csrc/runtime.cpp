@@ -28,7 +28,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 bool PlanKey::operator==(const PlanKey& o) const {
     if (n != o.n || w != o.w || method != o.method || t != o.t || a != o.a || b != o.b || nt != o.nt ||
-        iters != o.iters || swizzle != o.swizzle || tb_mix != o.tb_mix || c != o.c)
+        iters != o.iters || swizzle != o.swizzle || tb_mix != o.tb_mix || iter_mix != o.iter_mix || c != o.c)
         return false;
     for (int i = 0; i < n; i++)
         if (rows[i] != o.rows[i]) return false;
@@ -44,7 +44,7 @@ size_t PlanKeyHash::operator()(const PlanKey& k) const {
     };
     mixin((uint64_t)k.n | ((uint64_t)k.w << 8) | ((uint64_t)k.method << 16) | ((uint64_t)k.t << 24) |
           ((uint64_t)k.nt << 32) | ((uint64_t)k.iters << 48) | ((uint64_t)k.swizzle << 60) |
-          ((uint64_t)k.tb_mix << 62));
+          ((uint64_t)(k.tb_mix & 1) << 62) | ((uint64_t)k.iter_mix << 63));
     mixin(k.c ^ ((uint64_t)k.a << 56) ^ ((uint64_t)k.b << 48));
     for (int i = 0; i < k.n; i++) mixin(k.rows[i]);
     return (size_t)h;
@@ -90,6 +90,7 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
     key.iters = o.shape.iters;
     key.swizzle = o.swizzle;
     key.tb_mix = o.tb_mix;
+    key.iter_mix = o.iter_mix;
     key.c = c;
     for (int i = 0; i < n; i++) key.rows[i] = rows[i];
     {
@@ -179,6 +180,7 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     if (o->run_out) p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
     if (o->tile_order) p.tb_mix = (o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1);
+    p.iter_mix = (o->tile_order >> 3) & 1;
     if (o->threads > 0) p.shape.nt = o->threads;
     if (o->iters > 0) p.shape.iters = o->iters;
     return p;
@@ -197,9 +199,10 @@ int resolve_order(const bmmc_options_t* o) {
     return t & 1;  // XCD-contiguous tiles; the mixing bit lives in the plan
 }
 
-// Name of the tiled kernel instance, shared by both passes of a plan.
-static void kernel_name(char* buf, size_t len, const Plan& p) {
-    snprintf(buf, len, "k_tiled<%d,%d,%d>", p.w, p.shape.nt, p.shape.iters);
+// Name of the tiled kernel instance (template arguments), shared by both
+// passes of a plan.
+static void kernel_name(char* buf, size_t len, const Plan& p, int hints) {
+    snprintf(buf, len, "k_tiled<%d,%d,%d,%d>", p.w, p.shape.nt, p.shape.iters, hints);
 }
 
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
@@ -236,7 +239,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         const void* src = (k == 0) ? in : mid;
         void* dst = (k == plan.npass - 1) ? out : mid;
         const uint32_t ntiles = 1u << tab.ntb;
-        kernel_name(name, sizeof(name), plan);
+        kernel_name(name, sizeof(name), plan, hints);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
         e = launch_tiled(plan.w, ks.nt, ks.iters, hints, src, dst, tab, ntiles, grid,
                          (order & 1) ? (uint32_t)ds->xcds : 0u, stream);

@@ -19,7 +19,7 @@ int set_error(int status, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 
 struct PlanKey {
-    int n, w, method, t, a, b, nt, iters, swizzle, tb_mix;
+    int n, w, method, t, a, b, nt, iters, swizzle, tb_mix, iter_mix;
     uint64_t c;
     uint64_t rows[kMaxBits];
     bool operator==(const PlanKey& o) const;

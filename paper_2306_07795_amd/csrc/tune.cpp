@@ -194,7 +194,7 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
     uint64_t rows[64], c;
     random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, rows, &c);
 
-    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 2}, {256, 2}};
+    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}};
     double best = 1e30;
     bmmc_options_t bo;
     std::memset(&bo, 0, sizeof(bo));
@@ -212,7 +212,7 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         for (auto& ab : runs) {
             if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
             for (int hints : {4, 2, 3}) {
-                for (int order : {4, 2}) {
+                for (int order : {4, 2, 10}) {
                     for (int g = 0; g < 2; g++) {
                         bmmc_options_t o;
                         std::memset(&o, 0, sizeof(o));

@@ -309,6 +309,7 @@ def test_emulation_methods(method, n):
     {"swizzle": -1}, {"threads": 256, "iters": 16, "t": 7},
     {"run_in": 7, "run_out": 5}, {"run_in": 5, "run_out": 7}, {"threads": 512, "run_in": 7, "run_out": 6},
     {"tile_order": 2}, {"tile_order": 3, "run_in": 7, "run_out": 5},
+    {"tile_order": 10, "threads": 512, "iters": 8}, {"tile_order": 12, "threads": 1024, "iters": 4, "t": 6},
 ])
 def test_emulation_shapes(opts):
     n = 17
