@@ -362,8 +362,12 @@ def main():
     per_launch_ms = d["total_ms"] / d["launches"]
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    tbytes = traffic_for(dname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_for(dname),
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                # HBM bytes per launch from the rocprofv3 counters, as a rate over the same launch time
+                "traffic": None if tbytes is None else round(tbytes / (per_launch_ms * 1e-3) / 1e9, 1),
+                "traffic_bytes_per_launch": tbytes,
                 "kernel": dname, "launches": d["launches"], "mean_launch_ms": round(per_launch_ms, 5),
                 "bytes_per_launch": launch_bytes}
 
