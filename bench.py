@@ -254,6 +254,31 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0):
     }
 
 
+def transpose_sweep(n=25, w=4, steps=20):
+    """The paper's AMD experiment (Section 6, transpose time against the
+    number of columns at a fixed 2^25 elements), on this GPU: for every split
+    k, the 2^(n-k) x 2^k matrix transpose (bit-block swap, one tiled pass),
+    the naive kernel and the device copy."""
+    import torch
+    from paper_2306_07795_amd import binding as B
+    from synth import gen
+    nbytes = (1 << n) * w
+    x = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    copy_ms, _ = best_device_copy(x, y, nbytes, stream)
+    table = []
+    for k in range(n + 1):
+        rows = gen.block_swap_rows(n, k)
+        t_ms = timed(lambda: B.bmmc_permute(x, y, n, rows, 0, w, stream), steps, 2, stream)
+        nv_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, 0, w, stream), steps, 2, stream)
+        table.append({"k": k, "columns": 1 << k, "rows": 1 << (n - k),
+                      "tiled_us": round(t_ms * 1e3, 2), "tiled_GBps": round(gbps(nbytes, t_ms), 1),
+                      "tiled_pct_of_copy": round(100.0 * copy_ms / t_ms, 1),
+                      "naive_us": round(nv_ms * 1e3, 2), "naive_GBps": round(gbps(nbytes, nv_ms), 1)})
+    return {"n": n, "elem_bytes": w, "copy_us": round(copy_ms * 1e3, 2), "table": table}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,7 +296,12 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc runs of this "
                          "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--transpose-sweep", action="store_true",
+                    help="print the transpose-vs-columns table at 2^25 int32 and exit")
     args = ap.parse_args()
+    if args.transpose_sweep:
+        print(json.dumps(transpose_sweep()), flush=True)
+        return
     if args.traffic_from:
         n, w = WORKLOADS[args.workload][:2]
         print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w), indent=1))

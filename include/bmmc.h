@@ -190,6 +190,34 @@ int bmmc_plan_ex(const uint64_t* A_rows, uint64_t c, int n, int elem_bytes,
 int bmmc_factorize_ulp(const uint64_t* A_rows, int n, uint64_t* U, uint64_t* L, uint64_t* P,
                        uint64_t* T1, uint64_t* T2);
 
+/* ------------------------------------------------- host BMMC algebra */
+
+/* Composition (Section 3 fusion rule): bmmc(A, c) after bmmc(B, d) equals
+   bmmc(A.B, A.d XOR c).  Writes n rows to out_rows and the complement to
+   *out_c (out_rows may alias A_rows or B_rows).  Host only.
+   Errors: _ARG (NULL pointer, bits beyond n), _RANGE (n outside 1..64). */
+int bmmc_compose(const uint64_t* A_rows, uint64_t c, const uint64_t* B_rows, uint64_t d, int n,
+                 uint64_t* out_rows, uint64_t* out_c);
+
+/* Inverse: (A^-1, A^-1.c) undoes (A, c).  Host only.  Errors: _ARG,
+   _RANGE, _SINGULAR. */
+int bmmc_invert(const uint64_t* A_rows, uint64_t c, int n, uint64_t* out_rows, uint64_t* out_c);
+
+/* The BMMC that makes parm's two sub-arrays contiguous (Section 7.2): for a
+   nonzero n-bit mask with lowest set bit l, y_i = x_i for i < l,
+   y_i = x_(i+1) for l <= i < n-1, and y_(n-1) = x.mask (F_2 dot product), so
+   that parm mask f = bmmc(A^-1, 0) . parm 2^(n-1) f . bmmc(A, 0).  Writes A
+   to rows_out and A^-1 to inv_rows_out (either may be NULL).  Host only.
+   Errors: _ARG (mask zero or beyond n), _RANGE. */
+int bmmc_parm_matrix(uint64_t mask, int n, uint64_t* rows_out, uint64_t* inv_rows_out);
+
+/* Apply a sequence of `count` BMMCs (first one first) as ONE permutation:
+   the sequence is fused on the host with the composition rule and the
+   result is run as bmmc_permute would run it.  A_rows_seq holds count * n
+   rows, c_seq count complements.  Errors: as bmmc_permute. */
+int bmmc_permute_seq(const void* in, void* out, int n, int count, const uint64_t* A_rows_seq,
+                     const uint64_t* c_seq, int elem_bytes, void* stream);
+
 /* Host emulation of the tiled kernels' address arithmetic, for tests: runs
    the same plan, tile by tile and lane by lane, on host memory (in/out are
    HOST pointers here) and counts coalescing, LDS bank conflicts and LDS

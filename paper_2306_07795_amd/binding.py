@@ -101,6 +101,10 @@ def lib():
         "bmmc_factorize": (_i32, [P(_u64), _u64, _i32, P(Plan)]),
         "bmmc_factorize_t": (_i32, [P(_u64), _u64, _i32, _i32, _i32, P(Plan)]),
         "bmmc_emulate": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, P(Options), P(EmuStats)]),
+        "bmmc_compose": (_i32, [P(_u64), _u64, P(_u64), _u64, _i32, P(_u64), P(_u64)]),
+        "bmmc_invert": (_i32, [P(_u64), _u64, _i32, P(_u64), P(_u64)]),
+        "bmmc_parm_matrix": (_i32, [_u64, _i32, P(_u64), P(_u64)]),
+        "bmmc_permute_seq": (_i32, [_vp, _vp, _i32, _i32, P(_u64), P(_u64), _i32, _vp]),
         "bmmc_plan_ex": (_i32, [P(_u64), _u64, _i32, _i32, P(Options), P(Plan)]),
         "bmmc_factorize_ulp": (_i32, [P(_u64), _i32, P(_u64), P(_u64), P(_u64), P(_u64), P(_u64)]),
         "bmmc_permute": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
@@ -136,7 +140,8 @@ def lib():
 def exported_names():
     return [
         "bmmc_strerror", "bmmc_last_error", "bmmc_version", "bmmc_is_tiled", "bmmc_factorize",
-        "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
+        "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate",
+        "bmmc_compose", "bmmc_invert", "bmmc_parm_matrix", "bmmc_permute_seq", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
         "bmmc_copy", "bmmc_copy_ex", "bmmc_permute_batched", "bmmc_permute_batched_ex",
         "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
@@ -234,6 +239,41 @@ def bmmc_factorize_ulp(A_rows, n: int):
     _check(lib().bmmc_factorize_ulp(_rows(A_rows, n), n, outs["U"], outs["L"], outs["P"],
                                     outs["T1"], outs["T2"]))
     return {k: [int(v[i]) for i in range(n)] for k, v in outs.items()}
+
+
+def bmmc_compose(A_rows, c: int, B_rows, d: int, n: int):
+    """(rows, c) of bmmc(A, c) after bmmc(B, d)."""
+    out = (_u64 * max(n, 1))()
+    oc = _u64(0)
+    _check(lib().bmmc_compose(_rows(A_rows, n), c, _rows(B_rows, n), d, n, out, _c.byref(oc)))
+    return [int(out[i]) for i in range(n)], int(oc.value)
+
+
+def bmmc_invert(A_rows, c: int, n: int):
+    out = (_u64 * max(n, 1))()
+    oc = _u64(0)
+    _check(lib().bmmc_invert(_rows(A_rows, n), c, n, out, _c.byref(oc)))
+    return [int(out[i]) for i in range(n)], int(oc.value)
+
+
+def bmmc_parm_matrix(mask: int, n: int):
+    """(A, A^-1) rows for parm with this mask."""
+    a = (_u64 * max(n, 1))()
+    ai = (_u64 * max(n, 1))()
+    _check(lib().bmmc_parm_matrix(mask, n, a, ai))
+    return [int(a[i]) for i in range(n)], [int(ai[i]) for i in range(n)]
+
+
+def bmmc_permute_seq(inp, out, n: int, seq, elem_bytes: int, stream=None):
+    """seq: list of (rows, c), applied first to last, fused into one permutation."""
+    count = len(seq)
+    rows = (_u64 * max(count * n, 1))()
+    cs = (_u64 * max(count, 1))()
+    for k, (r, c) in enumerate(seq):
+        for i in range(n):
+            rows[k * n + i] = int(r[i])
+        cs[k] = int(c)
+    _check(lib().bmmc_permute_seq(_ptr(inp), _ptr(out), n, count, rows, cs, elem_bytes, _stream(stream)))
 
 
 def bmmc_emulate(inp, out, n: int, A_rows, c: int, elem_bytes: int, opts=None) -> dict:

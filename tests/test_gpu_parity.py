@@ -188,3 +188,38 @@ def test_profile_reports_launches():
     st = B.bmmc_profile_end()
     assert sum(v["launches"] for v in st.values()) == 6
     assert all(v["total_ms"] > 0 for v in st.values())
+
+
+@pytest.mark.parametrize("n,w", [(12, 4), (21, 4), (19, 8)])
+def test_fused_sequence_equals_steps(n, w):
+    """bmmc_permute_seq runs a fused sequence once; the oracle applies the
+    steps one after the other."""
+    seq = [gen.random_bmmc(n, 300 + k) for k in range(3)] + [(gen.bit_reversal_rows(n), 5)]
+    a = gen.data(n, w, 12)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    B.bmmc_permute_seq(x, y, n, seq, w, G.stream())
+    G.sync()
+    want = a
+    for rows, c in seq:
+        want = O.permute(want, n, rows, c)
+    assert np.array_equal(G.to_host(y, a), want)
+
+
+def test_parm_split_and_merge_on_device():
+    """parm mask f with f = reverse each half, built from two device BMMCs
+    around a plain half reversal (Section 7.2), against the parm definition."""
+    n, mask = 16, 0b1000100100010010
+    rows, inv = B.bmmc_parm_matrix(mask, n)
+    a = gen.data(n, 4, 21)
+    x, t = G.to_device(a), G.empty_like_bytes(a)
+    B.bmmc_permute(x, t, n, rows, 0, 4, G.stream())
+    halves = t.view(torch.int32).view(2, -1).flip(1).contiguous().view(torch.uint8).view(-1)
+    y = G.empty_like_bytes(a)
+    B.bmmc_permute(halves, y, n, inv, 0, 4, G.stream())
+    G.sync()
+    sub = np.array([bin(v & mask).count("1") & 1 for v in range(1 << n)])
+    want = a.copy()
+    for s in (0, 1):
+        idx = np.nonzero(sub == s)[0]
+        want[idx] = a[idx][::-1]
+    assert np.array_equal(G.to_host(y, a), want)
