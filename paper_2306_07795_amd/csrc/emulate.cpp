@@ -84,9 +84,9 @@ void emulate_pass(const PassTables& P, const KernelShape& ks, int w, const uint8
         uint32_t r = 0, yb = P.c_hi, gx = P.c_lds;
         for (uint32_t j = 0; j < P.ntb; j++)
             if ((tile >> j) & 1u) {
-                r ^= P.tb_in[j];
-                yb ^= P.tb_out[j];
-                gx ^= P.tb_lds[j];
+                r ^= P.tb[j][0];
+                yb ^= P.tb[j][1];
+                gx ^= P.tb[j][2];
             }
         std::fill(wr.begin(), wr.end(), 0);
         std::fill(rd.begin(), rd.end(), 0);

@@ -12,6 +12,10 @@
 namespace bmmc {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// The same vector in the global address space: accesses through these
+// pointers are global (not flat) loads and stores, which count only against
+// the vector-memory counter and so never hold up waits on LDS or scalar loads.
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
 
 template <int W> struct ElemT;
 template <> struct ElemT<1> { using T = uint8_t; };
@@ -32,12 +36,12 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // 16-byte global accesses; HINT bit 0 marks loads and bit 1 stores as
 // non-temporal (streamed, not kept in the caches).
 template <int HINT>
-__device__ __forceinline__ u32x4 ld16(const u32x4* p) {
+__device__ __forceinline__ u32x4 ld16(const g_u32x4* p) {
     if constexpr (HINT & 1) return __builtin_nontemporal_load(p);
     else return *p;
 }
 template <int HINT>
-__device__ __forceinline__ void st16(u32x4* p, u32x4 v) {
+__device__ __forceinline__ void st16(g_u32x4* p, u32x4 v) {
     if constexpr (HINT & 2) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
@@ -90,20 +94,27 @@ struct TileCtx {
         vlim = 1u << (P.d - LV);
     }
 
-    // Coset representative of a tile: XOR of the tile-selecting vectors of
-    // its set bits (uniform over the work-group: scalar work).
-    __device__ __forceinline__ uint32_t tile_in(const PassTables& P, uint32_t tile) const {
-        uint32_t r = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxTbBits; j++)
-            if (j < (int)P.ntb && ((tile >> j) & 1u)) r ^= P.tb_in[j];
-        return r;
+    // Per-tile parts: coset representative r (input), output base yb and LDS
+    // offset gx, each the XOR of the tile-selecting vectors of the tile
+    // index's set bits.  Uniform over the work-group: a short scalar loop
+    // over the set bits only, one 16-byte scalar load per bit.
+    struct Parts {
+        uint32_t r, yb, gx;
+    };
+    __device__ __forceinline__ Parts parts(const PassTables& P, uint32_t tile) const {
+        Parts p{0u, P.c_hi, P.c_lds};
+        for (uint32_t m = tile; m; m &= m - 1) {
+            const uint32_t j = __builtin_ctz(m);
+            p.r ^= P.tb[j][0];
+            p.yb ^= P.tb[j][1];
+            p.gx ^= P.tb[j][2];
+        }
+        return p;
     }
 
     // Read phase, global part: ITERS 16-byte loads, each inside one input run.
-    __device__ __forceinline__ void load(const PassTables& P, const u32x4* __restrict__ in, uint32_t tile,
+    __device__ __forceinline__ void load(const PassTables& P, const g_u32x4* __restrict__ in, uint32_t r,
                                          uint32_t tid, Vec16<W>* buf) const {
-        const uint32_t r = tile_in(P, tile);
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
@@ -127,24 +138,16 @@ struct TileCtx {
 
     // Write phase: gather each output vector from slots G(u), store it to
     // one output run at T.r XOR c XOR Y(u).
-    __device__ __forceinline__ void store(const PassTables& P, u32x4* __restrict__ out, const E* lds,
-                                          uint32_t tile, uint32_t tid) const {
-        uint32_t yb = P.c_hi, gx = P.c_lds;
-#pragma unroll
-        for (int j = 0; j < kMaxTbBits; j++) {
-            if (j < (int)P.ntb && ((tile >> j) & 1u)) {
-                yb ^= P.tb_out[j];
-                gx ^= P.tb_lds[j];
-            }
-        }
+    __device__ __forceinline__ void store(const PassTables& P, g_u32x4* __restrict__ out, const E* lds,
+                                          const Parts& pt, uint32_t tid) const {
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
-                const uint32_t g = gt ^ gx ^ lin_const<LV + LT, LI>(P.G, it);
+                const uint32_t g = gt ^ pt.gx ^ lin_const<LV + LT, LI>(P.G, it);
                 Vec16<W> o;
 #pragma unroll
                 for (int e = 0; e < VEC; e++) o.e[e] = lds[g ^ lin_const<0, LV>(P.G, e)];
-                const uint32_t y = yb ^ yt ^ lin_const<LV + LT, LI>(P.Y, it);
+                const uint32_t y = pt.yb ^ yt ^ lin_const<LV + LT, LI>(P.Y, it);
                 st16<HINT>(out + (y >> LV), o.v);
             }
         }
@@ -153,23 +156,29 @@ struct TileCtx {
     // Tiles first, first + step, ... below last.  The loads of the next tile
     // are issued right after the barrier that ends the current tile's LDS
     // writes, so they are in flight while the current tile is written out.
-    __device__ __forceinline__ void run_tiles(const PassTables& P, const u32x4* __restrict__ in,
-                                              u32x4* __restrict__ out, E* lds, uint32_t first,
+    __device__ __forceinline__ void run_tiles(const PassTables& P, const g_u32x4* __restrict__ in,
+                                              g_u32x4* __restrict__ out, E* lds, uint32_t first,
                                               uint32_t last, uint32_t step, uint32_t tid) const {
         if (first >= last) return;
         Vec16<W> buf[ITERS];
         uint32_t tile = first;
-        load(P, in, tile, tid, buf);
+        Parts cur = parts(P, tile);
+        load(P, in, cur.r, tid, buf);
         for (;;) {
             to_lds(P, lds, tid, buf);
             __syncthreads();
             const uint32_t next = tile + step;
             const bool more = next < last;
-            if (more) load(P, in, next, tid, buf);
-            store(P, out, lds, tile, tid);
+            Parts nxt = cur;
+            if (more) {
+                nxt = parts(P, next);
+                load(P, in, nxt.r, tid, buf);
+            }
+            store(P, out, lds, cur, tid);
             __syncthreads();
             if (!more) break;
             tile = next;
+            cur = nxt;
         }
     }
 };
@@ -194,7 +203,8 @@ k_tiled(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables 
     __shared__ typename C::E lds[1 << C::D];
     C ctx;
     ctx.init(P, threadIdx.x);
-    ctx.run_tiles(P, in, out, lds, logical_block(xcds), ntiles, gridDim.x, threadIdx.x);
+    ctx.run_tiles(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles, gridDim.x,
+                  threadIdx.x);
 }
 
 struct TiledEntry {
@@ -314,10 +324,10 @@ k_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, uint64_t nvec) {
     u32x4 v[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; k++)
-        if (base + k * 256 < nvec) v[k] = ld16<HINT>(in + base + k * 256);
+        if (base + k * 256 < nvec) v[k] = ld16<HINT>((const g_u32x4*)in + base + k * 256);
 #pragma unroll
     for (int k = 0; k < VPT; k++)
-        if (base + k * 256 < nvec) st16<HINT>(out + base + k * 256, v[k]);
+        if (base + k * 256 < nvec) st16<HINT>((g_u32x4*)out + base + k * 256, v[k]);
 }
 
 __global__ void k_copy_tail(const uint8_t* in, uint8_t* out, uint32_t count) {
@@ -388,7 +398,7 @@ __device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, ui
     using C = TileCtx<W, kBatchNT, kBatchIters, HINT>;
     C ctx;
     ctx.init(bp.tab, tid);
-    ctx.run_tiles(bp.tab, (const u32x4*)bp.in, (u32x4*)bp.out, (typename C::E*)lds_bytes, t0, t1, 1, tid);
+    ctx.run_tiles(bp.tab, (const g_u32x4*)bp.in, (g_u32x4*)bp.out, (typename C::E*)lds_bytes, t0, t1, 1, tid);
 }
 
 // range[phase] .. range[phase + 1] are this launch's items.

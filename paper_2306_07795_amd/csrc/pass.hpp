@@ -35,9 +35,11 @@ struct PassTables {
     uint32_t F[kMaxTileBits];    // LDS slot of read-coordinate bit k
     uint32_t Y[kMaxTileBits];    // output offset of write-coordinate bit k
     uint32_t G[kMaxTileBits];    // LDS slot of write-coordinate bit k
-    uint32_t tb_in[kMaxTbBits];  // input offset of tile-index bit j
-    uint32_t tb_out[kMaxTbBits]; // output offset of tile-index bit j (low b bits cleared)
-    uint32_t tb_lds[kMaxTbBits]; // LDS offset absorbing the low b bits of T.tb_in[j]
+    // Per tile-index bit j: tb[j][0] input offset, tb[j][1] output offset
+    // (low b bits cleared), tb[j][2] LDS offset absorbing the low b bits of
+    // T.tb[j][0]; tb[j][3] unused.  Interleaved so that one 16-byte scalar
+    // load fetches all three.
+    uint32_t tb[kMaxTbBits][4];
 };
 
 // One work item of the batched persistent kernel: a range of tiles of one

@@ -342,9 +342,9 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
     }
     for (int i = 0; i < ntb; i++) {
         uint64_t col = T.apply(tbv[i]);
-        tab.tb_in[i] = (uint32_t)tbv[i];
-        tab.tb_out[i] = (uint32_t)(col & ~low_mask(b));
-        tab.tb_lds[i] = gmap(col & low_mask(b));
+        tab.tb[i][0] = (uint32_t)tbv[i];
+        tab.tb[i][1] = (uint32_t)(col & ~low_mask(b));
+        tab.tb[i][2] = gmap(col & low_mask(b));
     }
     tab.c_hi = (uint32_t)(c & ~low_mask(b));
     tab.c_lds = gmap(c & low_mask(b));
