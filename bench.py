@@ -195,18 +195,27 @@ def bench_batched(count=1024, reps=50, seed=0):
             out.append(a.elapsed_time(b))
         return np.array(out)
 
-    batched = lat(lambda: B.bmmc_permute_batched(items, stream), reps)
+    # resident batch: one graph replay per launch (the descriptors, plans,
+    # scratch and graph were made once)
+    pb = B.bmmc_batch_create(items, tuned)
+    pb.launch(stream)
+    resident = lat(lambda: pb.launch(stream), reps)
+    # one-shot batched call: host planning (cached) and table upload included
+    oneshot = lat(lambda: B.bmmc_permute_batched(items, stream, tuned), max(5, reps // 5))
 
     def separate():
         for it in items:
             B.bmmc_permute(it[0], it[1], it[2], it[4], it[5], 4, stream)
 
     sep = lat(separate, max(5, reps // 5))
-    med = float(np.median(batched))
+    pb.close()
+    med = float(np.median(resident))
     return {
         "arrays": count, "bytes_per_side": total,
         "GBps": round(gbps(total, med), 1),
-        "p50_ms": round(med, 4), "p99_ms": round(float(np.percentile(batched, 99)), 4),
+        "p50_ms": round(med, 4), "p99_ms": round(float(np.percentile(resident, 99)), 4),
+        "oneshot_p50_ms": round(float(np.median(oneshot)), 4),
+        "oneshot_GBps": round(gbps(total, float(np.median(oneshot))), 1),
         "separate_launches_GBps": round(gbps(total, float(np.median(sep))), 1),
         "separate_p50_ms": round(float(np.median(sep)), 4),
         "separate_p99_ms": round(float(np.percentile(sep, 99)), 4),

@@ -268,6 +268,18 @@ int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream);
 int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count,
                             const bmmc_batch_options_t* opts, void* stream);
 
+/* A batch kept resident on the device: plans, the device descriptor table,
+   a scratch array for the two-pass arrays and the captured graph are made
+   once; each bmmc_batch_launch is one graph replay (plus the single-array
+   launches of arrays the persistent kernel does not take).  The descriptors'
+   buffers must stay valid until bmmc_batch_destroy; launches of one handle
+   must not overlap (they share the scratch and the work counters).
+   Errors: as bmmc_permute_batched, plus _NOMEM for the owned buffers. */
+int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc_batch_options_t* opts,
+                      void** handle_out);
+int bmmc_batch_launch(void* handle, void* stream);
+int bmmc_batch_destroy(void* handle);
+
 /* ------------------------------------------------------------- autotuner */
 
 /* Time the available tile shapes (threads x iterations), run widths t and

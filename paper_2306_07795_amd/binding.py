@@ -114,6 +114,9 @@ def lib():
         "bmmc_copy_ex": (_i32, [_vp, _vp, _c.c_size_t, _i32, _i32, _vp]),
         "bmmc_permute_batched": (_i32, [P(Desc), _i32, _vp]),
         "bmmc_permute_batched_ex": (_i32, [P(Desc), _i32, P(BatchOptions), _vp]),
+        "bmmc_batch_create": (_i32, [P(Desc), _i32, P(BatchOptions), P(_vp)]),
+        "bmmc_batch_launch": (_i32, [_vp, _vp]),
+        "bmmc_batch_destroy": (_i32, [_vp]),
         "bmmc_profile_begin": (_i32, []),
         "bmmc_profile_end": (_i32, [P(KernelStat), _i32]),
         "bmmc_autotune_batched": (_i32, [P(Desc), _i32, _vp, _i32, P(BatchOptions), P(_dbl)]),
@@ -143,6 +146,7 @@ def exported_names():
         "bmmc_factorize_t", "bmmc_plan_ex", "bmmc_factorize_ulp", "bmmc_emulate",
         "bmmc_compose", "bmmc_invert", "bmmc_parm_matrix", "bmmc_permute_seq", "bmmc_permute", "bmmc_permute_ex", "bmmc_permute_naive",
         "bmmc_copy", "bmmc_copy_ex", "bmmc_permute_batched", "bmmc_permute_batched_ex",
+        "bmmc_batch_create", "bmmc_batch_launch", "bmmc_batch_destroy",
         "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
@@ -309,20 +313,29 @@ def bmmc_copy_ex(inp, out, nbytes: int, vpt: int = 4, hints: int = 0, stream=Non
 
 def make_descs(items):
     """items: iterable of (in, out, n, elem_bytes, A_rows, c).  Returns a
-    ctypes array of Desc plus the row arrays it points into (keep both alive)."""
+    ctypes array of Desc plus the row storage it points into (keep both
+    alive) and the count.  All rows go into one uint64 buffer."""
+    import numpy as np
     items = list(items)
-    arr = (Desc * max(len(items), 1))()
-    keep = []
-    for k, (i, o, n, w, rows, c) in enumerate(items):
-        r = _rows(rows, n)
-        keep.append(r)
-        arr[k].in_ = _ptr(i)
-        arr[k].out = _ptr(o)
-        arr[k].n = n
-        arr[k].elem_bytes = w
-        arr[k].A_rows = _c.cast(r, _c.POINTER(_u64))
-        arr[k].c = c
-    return arr, keep, len(items)
+    count = len(items)
+    arr = (Desc * max(count, 1))()
+    total = sum(int(it[2]) for it in items)
+    rows = np.zeros(max(total, 1), dtype=np.uint64)
+    base = rows.ctypes.data
+    off = 0
+    for k, (i, o, n, w, r, c) in enumerate(items):
+        n = int(n)
+        if n:
+            rows[off:off + n] = np.asarray([int(v) for v in r[:n]], dtype=np.uint64)
+        d = arr[k]
+        d.in_ = _ptr(i)
+        d.out = _ptr(o)
+        d.n = n
+        d.elem_bytes = w
+        d.A_rows = _c.cast(_c.c_void_p(base + 8 * off), _c.POINTER(_u64))
+        d.c = c
+        off += n
+    return arr, rows, count
 
 
 def _batch_options(opts):
@@ -334,6 +347,35 @@ def _batch_options(opts):
     for k, v in dict(opts).items():
         setattr(o, k, int(v))
     return _c.byref(o)
+
+
+class PreparedBatch:
+    """A batch resident on the device (bmmc_batch_create); launch() replays
+    its graph.  The caller keeps the arrays alive until close()."""
+
+    def __init__(self, items, opts=None):
+        arr, keep, count = make_descs(items)
+        h = _vp()
+        _check(lib().bmmc_batch_create(arr, count, _batch_options(opts), _c.byref(h)))
+        self.handle = h.value
+
+    def launch(self, stream=None):
+        _check(lib().bmmc_batch_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _check(lib().bmmc_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bmmc_batch_create(items, opts=None) -> PreparedBatch:
+    return PreparedBatch(items, opts)
 
 
 def bmmc_permute_batched(items, stream=None, opts=None):

@@ -104,10 +104,9 @@ BatchState* batch_state(hipStream_t stream, int device) {
     return bs;
 }
 
-// Enqueue [clear heads] -> phase 0 -> phase 1 on `s` (captured or not).
-hipError_t enqueue_phases(BatchState* bs, uint32_t grid, int hints, hipStream_t s) {
-    Layout L = layout_for(bs->cap_passes, bs->cap_items);
-    uint8_t* d = (uint8_t*)bs->dev;
+// Enqueue [clear heads] -> phase 0 -> phase 1 on `s` (captured or not) for
+// the device table at d with layout L.
+hipError_t enqueue_phases_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipStream_t s) {
     uint32_t* heads = (uint32_t*)(d + L.heads_off);
     const BatchPass* passes = (const BatchPass*)(d + L.passes_off);
     const BatchItem* items = (const BatchItem*)(d + L.items_off);
@@ -118,12 +117,8 @@ hipError_t enqueue_phases(BatchState* bs, uint32_t grid, int hints, hipStream_t 
     return e;
 }
 
-int build_graph(BatchState* bs, uint32_t grid, int hints) {
-    if (bs->exec && bs->exec_grid == grid && bs->exec_hints == hints) return BMMC_OK;
-    if (bs->exec) {
-        hipGraphExecDestroy(bs->exec);
-        bs->exec = nullptr;
-    }
+// Capture the three launches into an executable graph.
+int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipGraphExec_t* out) {
     hipStream_t cap;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -132,20 +127,109 @@ int build_graph(BatchState* bs, uint32_t grid, int hints) {
         hipStreamDestroy(cap);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    enqueue_phases(bs, grid, hints, cap);
+    enqueue_phases_at(d, L, grid, hints, cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
     hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&bs->exec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
-        bs->exec = nullptr;
+        *out = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
     }
+    return BMMC_OK;
+}
+
+int build_graph(BatchState* bs, uint32_t grid, int hints) {
+    if (bs->exec && bs->exec_grid == grid && bs->exec_hints == hints) return BMMC_OK;
+    if (bs->exec) {
+        hipGraphExecDestroy(bs->exec);
+        bs->exec = nullptr;
+    }
+    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, &bs->exec);
+    if (st != BMMC_OK) return st;
     bs->exec_grid = grid;
     bs->exec_hints = hints;
     return BMMC_OK;
+}
+
+// The arrays that go through the persistent kernel, in queue order.
+// 0: largest first (the short items at the end even out the finish);
+// 1: input order.
+std::vector<size_t> work_order(const std::vector<BatchArray>& arrays, int order) {
+    std::vector<size_t> work;
+    for (size_t i = 0; i < arrays.size(); i++)
+        if (!arrays[i].single) work.push_back(i);
+    if (order != 1)
+        std::stable_sort(work.begin(), work.end(),
+                         [&](size_t x, size_t y) { return arrays[x].bytes > arrays[y].bytes; });
+    return work;
+}
+
+void table_counts(const std::vector<BatchArray>& arrays, const std::vector<size_t>& work, uint32_t chunk,
+                  size_t* npasses, size_t* nitems) {
+    *npasses = *nitems = 0;
+    for (size_t a : work) {
+        const Plan& p = *arrays[a].plan;
+        *npasses += p.npass;
+        for (int k = 0; k < p.npass; k++) *nitems += ((1u << p.pass[k].tab.ntb) + chunk - 1) / chunk;
+    }
+}
+
+// Write the range header, the pass table and the work items (phase 0: every
+// first pass; phase 1: the second passes) into the image h with layout L.
+// Returns the number of passes; *nitems and *moved receive the item count
+// and the algorithmic bytes of one launch.
+uint32_t fill_table(const std::vector<BatchArray>& arrays, const std::vector<size_t>& work, uint32_t chunk,
+                    uint8_t* h, const Layout& L, size_t* nitems, double* moved) {
+    BatchPass* hp = (BatchPass*)(h + L.passes_off);
+    BatchItem* hi = (BatchItem*)(h + L.items_off);
+    uint32_t pidx = 0;
+    *moved = 0;
+    std::vector<uint32_t> first_pass(arrays.size(), 0);
+    for (size_t a : work) {
+        const BatchArray& ba = arrays[a];
+        const Plan& p = *ba.plan;
+        first_pass[a] = pidx;
+        for (int k = 0; k < p.npass; k++) {
+            BatchPass& bp = hp[pidx++];
+            std::memset(&bp, 0, sizeof(bp));
+            bp.in = (k == 0) ? ba.in : ba.scratch;
+            bp.out = (k == p.npass - 1) ? ba.out : ba.scratch;
+            bp.w = (uint32_t)p.w;
+            bp.tab = p.pass[k].tab;
+        }
+        *moved += 2.0 * (double)ba.bytes;
+    }
+    size_t ni = 0;
+    auto emit = [&](size_t a, int k) {
+        const Plan& p = *arrays[a].plan;
+        const uint32_t ntiles = 1u << p.pass[k].tab.ntb;
+        for (uint32_t t0 = 0; t0 < ntiles; t0 += chunk) {
+            BatchItem& it = hi[ni++];
+            std::memset(&it, 0, sizeof(it));
+            it.pass = first_pass[a] + (uint32_t)k;
+            it.tile_begin = t0;
+            it.tile_end = std::min(ntiles, t0 + chunk);
+        }
+    };
+    for (size_t a : work) emit(a, 0);
+    const uint32_t phase0_end = (uint32_t)ni;
+    for (size_t a : work)
+        if (arrays[a].plan->npass == 2) emit(a, 1);
+    uint32_t* range = (uint32_t*)h;
+    range[0] = 0;
+    range[1] = phase0_end;
+    range[2] = (uint32_t)ni;
+    *nitems = ni;
+    return pidx;
+}
+
+int resolve_batch_hints(const bmmc_batch_options_t& o, double moved) {
+    // Non-temporal accesses pay off once the data outgrows the last-level cache.
+    if (o.hints > 0) return (o.hints & 4) ? 0 : (o.hints & 3);
+    return moved >= 2.0 * (double)((size_t)64 << 20) ? 3 : 0;
 }
 
 }  // namespace
@@ -219,33 +303,18 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
                     hipStream_t stream) {
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
     int st;
-    std::vector<size_t> work;
-    double moved = 0;
     for (size_t i = 0; i < arrays.size(); i++) {
         if (arrays[i].single) {
             st = enqueue_plan(ds, *arrays[i].plan, arrays[i].in, arrays[i].out, stream, 0);
             if (st != BMMC_OK) return st;
-        } else {
-            if (arrays[i].plan->npass == 2 && !arrays[i].scratch)
-                return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");
-            work.push_back(i);
-            moved += 2.0 * (double)arrays[i].bytes;
+        } else if (arrays[i].plan->npass == 2 && !arrays[i].scratch) {
+            return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");
         }
     }
+    const std::vector<size_t> work = work_order(arrays, o.order);
     if (work.empty()) return BMMC_OK;
-
-    // Queue order inside each phase.  0: largest arrays first (the short
-    // items at the end even out the finish); 1: input order.
-    if (o.order != 1)
-        std::stable_sort(work.begin(), work.end(),
-                         [&](size_t x, size_t y) { return arrays[x].bytes > arrays[y].bytes; });
-
-    size_t npasses = 0, nitems = 0;
-    for (size_t a : work) {
-        const Plan& p = *arrays[a].plan;
-        npasses += p.npass;
-        for (int k = 0; k < p.npass; k++) nitems += ((1u << p.pass[k].tab.ntb) + chunk - 1) / chunk;
-    }
+    size_t npasses, nitems;
+    table_counts(arrays, work, chunk, &npasses, &nitems);
     BatchState* bs = batch_state(stream, ds->device);
     st = ensure_capacity(bs, npasses, nitems);
     if (st != BMMC_OK) return st;
@@ -253,51 +322,14 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
         hipError_t e = hipEventSynchronize(bs->staged);  // staging buffer free again
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     }
-    Layout L = layout_for(bs->cap_passes, bs->cap_items);
+    const Layout L = layout_for(bs->cap_passes, bs->cap_items);
     uint8_t* h = (uint8_t*)bs->host;
-    BatchPass* hp = (BatchPass*)(h + L.passes_off);
-    BatchItem* hi = (BatchItem*)(h + L.items_off);
-
-    // Pass table.
-    uint32_t pidx = 0;
-    std::vector<uint32_t> first_pass(arrays.size(), 0);
-    for (size_t a : work) {
-        const BatchArray& ba = arrays[a];
-        const Plan& p = *ba.plan;
-        first_pass[a] = pidx;
-        for (int k = 0; k < p.npass; k++) {
-            BatchPass& bp = hp[pidx++];
-            std::memset(&bp, 0, sizeof(bp));
-            bp.in = (k == 0) ? ba.in : ba.scratch;
-            bp.out = (k == p.npass - 1) ? ba.out : ba.scratch;
-            bp.w = (uint32_t)p.w;
-            bp.tab = p.pass[k].tab;
-        }
-    }
-    // Work items, phase 0 then phase 1, each a range of `chunk` tiles.
-    size_t ni = 0;
-    auto emit = [&](size_t a, int k) {
-        const Plan& p = *arrays[a].plan;
-        const uint32_t ntiles = 1u << p.pass[k].tab.ntb;
-        for (uint32_t t0 = 0; t0 < ntiles; t0 += chunk) {
-            BatchItem& it = hi[ni++];
-            std::memset(&it, 0, sizeof(it));
-            it.pass = first_pass[a] + (uint32_t)k;
-            it.tile_begin = t0;
-            it.tile_end = std::min(ntiles, t0 + chunk);
-        }
-    };
-    for (size_t a : work) emit(a, 0);
-    const uint32_t phase0_end = (uint32_t)ni;
-    for (size_t a : work)
-        if (arrays[a].plan->npass == 2) emit(a, 1);
-    uint32_t* range = (uint32_t*)h;
-    range[0] = 0;
-    range[1] = phase0_end;
-    range[2] = (uint32_t)ni;
+    size_t ni;
+    double moved;
+    const uint32_t np = fill_table(arrays, work, chunk, h, L, &ni, &moved);
 
     // Upload only what is used, then launch.
-    hipError_t e = hipMemcpyAsync(bs->dev, bs->host, L.passes_off + pidx * sizeof(BatchPass),
+    hipError_t e = hipMemcpyAsync(bs->dev, bs->host, L.passes_off + np * sizeof(BatchPass),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync((uint8_t*)bs->dev + L.items_off, h + L.items_off, ni * sizeof(BatchItem),
@@ -308,9 +340,7 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
 
     const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
                                            : (uint32_t)(ds->cu_count * batched_occupancy());
-    // Non-temporal accesses pay off once the data outgrows the last-level cache.
-    const int hints = o.hints > 0 ? ((o.hints & 4) ? 0 : (o.hints & 3))
-                                  : (moved >= 2.0 * (double)((size_t)64 << 20) ? 3 : 0);
+    const int hints = resolve_batch_hints(o, moved);
     LaunchScope ls(ds, stream, "k_batched", moved);
     if (o.use_graph >= 0) {
         st = build_graph(bs, grid, hints);
@@ -318,7 +348,7 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
         e = hipGraphLaunch(bs->exec, stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        e = enqueue_phases(bs, grid, hints, stream);
+        e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     return BMMC_OK;
@@ -382,4 +412,127 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
 
 extern "C" int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream) {
     return bmmc_permute_batched_ex(descs, count, nullptr, stream);
+}
+
+// ------------------------------------------------------------ prepared batches
+
+namespace bmmc {
+
+struct PreparedBatch {
+    DeviceState* ds = nullptr;
+    std::vector<BatchArray> arrays;
+    void* table = nullptr;    // device table (range, passes, items, heads)
+    void* scratch = nullptr;  // owned scratch of the two-pass arrays
+    hipGraphExec_t exec = nullptr;
+    uint32_t grid = 0;
+    int hints = 0;
+    bool use_graph = true;
+    Layout L{};
+    double moved = 0;
+};
+
+}  // namespace bmmc
+
+extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc_batch_options_t* opts,
+                                 void** handle_out) {
+    if (!handle_out) return set_error(BMMC_ERR_ARG, "handle_out is NULL");
+    int st = batch_validate(descs, count);
+    if (st != BMMC_OK) return st;
+    if (count == 0) return set_error(BMMC_ERR_ARG, "empty batch");
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    bmmc_batch_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    else tuned_batch_options(batch_signature(descs, count), &o);
+    const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
+
+    auto* pb = new PreparedBatch();
+    pb->ds = ds;
+    pb->arrays.resize(count);
+    size_t scratch_total = 0;
+    std::vector<size_t> offs(count, 0);
+    for (int i = 0; i < count; i++) {
+        st = plan_batch_array(ds, descs[i], o.method, &pb->arrays[i]);
+        if (st != BMMC_OK) {
+            delete pb;
+            return set_error(st, "array %d: %s", i, bmmc_last_error());
+        }
+        if (!pb->arrays[i].single && pb->arrays[i].plan->npass == 2) {
+            offs[i] = scratch_total;
+            scratch_total += (pb->arrays[i].bytes + 255) / 256 * 256;
+        }
+    }
+    auto fail = [&](int code) {
+        if (pb->scratch) hipFree(pb->scratch);
+        if (pb->table) hipFree(pb->table);
+        delete pb;
+        return code;
+    };
+    if (scratch_total) {
+        hipError_t e = hipMalloc(&pb->scratch, scratch_total);
+        if (e != hipSuccess) {
+            pb->scratch = nullptr;
+            (void)hipGetLastError();
+            return fail(set_error(BMMC_ERR_NOMEM, "batch scratch of %zu bytes", scratch_total));
+        }
+        for (int i = 0; i < count; i++)
+            if (!pb->arrays[i].single && pb->arrays[i].plan->npass == 2)
+                pb->arrays[i].scratch = (uint8_t*)pb->scratch + offs[i];
+    }
+    const std::vector<size_t> work = work_order(pb->arrays, o.order);
+    size_t npasses, nitems;
+    table_counts(pb->arrays, work, chunk, &npasses, &nitems);
+    pb->L = layout_for(npasses, nitems);
+    std::vector<uint8_t> image(pb->L.total, 0);
+    size_t ni;
+    fill_table(pb->arrays, work, chunk, image.data(), pb->L, &ni, &pb->moved);
+    hipError_t e = hipMalloc(&pb->table, pb->L.total);
+    if (e != hipSuccess) {
+        pb->table = nullptr;
+        (void)hipGetLastError();
+        return fail(set_error(BMMC_ERR_NOMEM, "batch table of %zu bytes", pb->L.total));
+    }
+    e = hipMemcpy(pb->table, image.data(), pb->L.total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy (batch table)"));
+    pb->grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy());
+    pb->hints = resolve_batch_hints(o, pb->moved);
+    pb->use_graph = o.use_graph >= 0;
+    if (!work.empty() && pb->use_graph) {
+        st = capture_graph_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, &pb->exec);
+        if (st != BMMC_OK) return fail(st);
+    }
+    *handle_out = pb;
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
+    PreparedBatch* pb = (PreparedBatch*)handle;
+    if (!pb) return set_error(BMMC_ERR_ARG, "NULL handle");
+    hipStream_t stream = (hipStream_t)stream_;
+    DeviceState* ds = pb->ds;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    for (auto& ba : pb->arrays) {
+        if (!ba.single) continue;
+        int st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, stream, 0);
+        if (st != BMMC_OK) return st;
+    }
+    bool any = false;
+    for (auto& ba : pb->arrays) any |= !ba.single;
+    if (!any) return BMMC_OK;
+    LaunchScope ls(ds, stream, "k_batched", pb->moved);
+    hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
+                                 : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, stream);
+    return e == hipSuccess ? BMMC_OK : hip_fail(e, "batch launch");
+}
+
+extern "C" int bmmc_batch_destroy(void* handle) {
+    PreparedBatch* pb = (PreparedBatch*)handle;
+    if (!pb) return set_error(BMMC_ERR_ARG, "NULL handle");
+    hipDeviceSynchronize();
+    if (pb->exec) hipGraphExecDestroy(pb->exec);
+    if (pb->table) hipFree(pb->table);
+    if (pb->scratch) hipFree(pb->scratch);
+    delete pb;
+    return BMMC_OK;
 }

@@ -221,3 +221,25 @@ def test_server_budget_admission_and_caller_outputs():
             B.bmmc_server_submit(srv, work[0][4], work[0][5], 22, gen.identity_rows(22), 0, 4)
     finally:
         B.bmmc_server_destroy(srv)
+
+
+def test_prepared_batch_replays():
+    """A resident batch (plans, table, scratch and graph made once) replayed
+    with fresh inputs each time; every array checked each time."""
+    rng = np.random.default_rng(31)
+    sizes = [int(v) for v in rng.integers(0, 21, size=40)]
+    widths = [int(v) for v in rng.choice([4, 8, 16, 2], size=40)]
+    arrays = make_batch(sizes, widths, 31)
+    pb = B.bmmc_batch_create(items(arrays))
+    try:
+        for rep in range(3):
+            for k, ar in enumerate(arrays):
+                ar["a"] = gen.data(ar["n"], ar["w"], 500 * rep + k)
+                ar["x"].copy_(torch.from_numpy(ar["a"].view(np.uint8).reshape(-1)).to(G.dev()))
+                ar["y"].zero_()
+            torch.cuda.synchronize()
+            pb.launch(G.stream())
+            G.sync()
+            check_all(arrays)
+    finally:
+        pb.close()
