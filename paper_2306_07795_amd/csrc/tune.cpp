@@ -285,12 +285,16 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
                 o.chunk_tiles = chunk;
                 o.order = order;
                 o.workgroups = ds->cu_count * occ * g / 2;
-                st = bmmc_permute_batched_ex(descs, count, &o, stream);  // warm-up
+                // time graph replays of a resident batch: device time only
+                void* pb = nullptr;
+                st = bmmc_batch_create(descs, count, &o, &pb);
                 if (st != BMMC_OK) return st;
+                bmmc_batch_launch(pb, stream);  // warm-up
                 hipEventRecord(tm.a, stream);
-                for (int r = 0; r < reps; r++) bmmc_permute_batched_ex(descs, count, &o, stream);
+                for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
                 hipEventRecord(tm.b, stream);
                 hipEventSynchronize(tm.b);
+                bmmc_batch_destroy(pb);
                 float ms = 0;
                 hipEventElapsedTime(&ms, tm.a, tm.b);
                 const double per = ms / reps;
