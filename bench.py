@@ -2,19 +2,21 @@
 """Throughput of BMMC permutations on one MI355X.
 
 Default workload: a uniformly random invertible 26 x 26 matrix over F_2 with a
-random complement (seed 0), applied to 2^26 int32 elements drawn from seed 0
-by the paper's scheme: factorization into two tiled BMMCs, each run as one
-LDS-staged pass (through a scratch array).  One step is one whole permutation
-(both passes) of the HBM-resident array.
+random complement (seed 0), applied to 2^26 int32 elements drawn from seed 0.
+The timed path is the library's default call with autotuned options: one
+LDS-staged pass over the HBM-resident array (a general tile; tiled matrices
+take the paper's tiled pass), unless the tuner found the paper's two tiled
+passes faster.  One step is one whole permutation.  The paper's two-pass
+scheme (Section 5.2) on the same input is timed beside it.
 
 Prints ONE JSON line.  `value` is effective throughput in GB/s (decimal):
 algorithmic bytes (one read plus one write of the array, 2 * 2^n * w) per step
 time.  Beside it: the best same-session device copy and the HBM peak as
-fractions, the traffic rate (both passes' bytes, the paper's accounting), the
-roofline of the tiled-pass kernel, the general one-pass tile, the naive lower
-bound, the batched form (1024 arrays, one graph launch, against 1024 separate
-calls; p50/p99 of the batch latency), the served form (Poisson arrivals,
-p50/p99 request latency) and the CPU oracle's rate on this host.
+fractions, the roofline of the dominant kernel, the paper's two-pass scheme,
+the naive lower bound, the batched form (1024 arrays, one graph launch,
+against 1024 separate calls; p50/p99 of the batch latency), the served form
+(Poisson arrivals, p50/p99 request latency) and the CPU oracle's rate on this
+host.
 """
 from __future__ import annotations
 
@@ -34,14 +36,14 @@ HBM_PEAK_GBPS = 8000.0
 WORKLOADS = {
     # name: (n, elem_bytes, matrix kind, description)
     "random26": (26, 4, "random", "random BMMC on 2^26 int32 (A uniform invertible 26x26 over F_2, "
-                                  "random c, seed 0), two tiled passes"),
-    "random28": (28, 4, "random", "random BMMC on 2^28 int32 (seed 0), two tiled passes"),
-    "random27x8": (27, 8, "random", "random BMMC on 2^27 int64 (seed 0), two tiled passes"),
-    "bitrev28": (28, 4, "bitrev", "bit reversal of 2^28 int32, one tiled pass"),
-    "bitrev27x8": (27, 8, "bitrev", "bit reversal of 2^27 int64, one tiled pass"),
-    "swap28": (28, 4, "swap", "2^14 x 2^14 int32 matrix transpose (bit-block swap), one tiled pass"),
-    "swap27x8": (27, 8, "swap", "2^13 x 2^14 int64 matrix transpose (bit-block swap), one tiled pass"),
-    "bitrev20": (20, 4, "bitrev", "bit reversal of 2^20 int32 (cache resident), one tiled pass"),
+                                  "random c, seed 0)"),
+    "random28": (28, 4, "random", "random BMMC on 2^28 int32 (seed 0)"),
+    "random27x8": (27, 8, "random", "random BMMC on 2^27 int64 (seed 0)"),
+    "bitrev28": (28, 4, "bitrev", "bit reversal of 2^28 int32"),
+    "bitrev27x8": (27, 8, "bitrev", "bit reversal of 2^27 int64"),
+    "swap28": (28, 4, "swap", "2^14 x 2^14 int32 matrix transpose (bit-block swap)"),
+    "swap27x8": (27, 8, "swap", "2^13 x 2^14 int64 matrix transpose (bit-block swap)"),
+    "bitrev20": (20, 4, "bitrev", "bit reversal of 2^20 int32 (cache resident)"),
 }
 
 
@@ -162,6 +164,36 @@ def best_device_copy(x, y, nbytes, stream):
     ms = timed(lambda: y.copy_(x), 10, 2, stream)
     best = min(best, (ms, "hipMemcpy device to device"))
     return best
+
+
+def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True):
+    """The paper's scheme on the same input: the factorization into tiled
+    BMMCs, two LDS-staged passes through scratch (Section 5.2), tuned the
+    same way; with its dominant kernel's per-launch rate."""
+    from paper_2306_07795_amd import binding as B
+    nbytes = (1 << n) * w
+    opts = {"method": B.METHOD_TILED}
+    if tune:
+        opts, _ = B.bmmc_autotune(n, w, B.METHOD_TILED, stream, 3)
+    passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
+    for _ in range(3):
+        B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
+    torch_sync()
+    B.bmmc_profile_begin()
+    ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 0, stream)
+    ks = B.bmmc_profile_end()
+    kname, k = max(ks.items(), key=lambda kv: kv[1]["total_ms"])
+    per_launch = k["total_ms"] / k["launches"]
+    v = gbps(nbytes, ms)
+    return {"GBps": round(v, 1), "passes": passes, "pct_of_device_copy": round(100.0 * v / dev_copy, 2),
+            "traffic_pct_of_device_copy": round(100.0 * v * passes / dev_copy, 2),
+            "kernel": kname, "kernel_GBps": round(k["bytes"] / k["launches"] / (per_launch * 1e-3) / 1e9, 1),
+            "options": opts}
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def bench_batched(count=1024, reps=50, seed=0):
@@ -294,8 +326,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="random26", choices=sorted(WORKLOADS))
-    ap.add_argument("--method", default="auto", choices=["auto", "onepass", "naive"])
+    ap.add_argument("--method", default="auto", choices=["auto", "tiled", "onepass", "naive"])
     ap.add_argument("--no-tune", action="store_true", help="time the library defaults, no autotuning")
+    ap.add_argument("--options-from", metavar="BENCH_JSON",
+                    help="no autotuning: take the options from the JSON line of an earlier run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed permutation and the copy bound (for counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
@@ -329,9 +365,8 @@ def main():
 
     n, w, kind, desc = WORKLOADS[args.workload]
     rows, c = matrix(kind, n)
-    method = {"auto": B.METHOD_AUTO, "onepass": B.METHOD_ONEPASS, "naive": B.METHOD_NAIVE}[args.method]
-    plan = B.bmmc_factorize_t(rows, c, n, 0, w) if method == B.METHOD_AUTO else None
-    passes = plan.nfactors if plan is not None else 1
+    method = {"auto": B.METHOD_AUTO, "tiled": B.METHOD_TILED, "onepass": B.METHOD_ONEPASS,
+              "naive": B.METHOD_NAIVE}[args.method]
 
     a = gen.data(n, w, 0)
     nbytes = a.nbytes
@@ -342,10 +377,14 @@ def main():
 
     opts = {"method": method}
     tuned = None
-    if not args.no_tune and method != B.METHOD_NAIVE:
+    if args.options_from:
+        with open(args.options_from) as fh:
+            tuned = json.loads(fh.read().strip().splitlines()[-1])["config"]["options"]
+    elif not args.no_tune and method != B.METHOD_NAIVE:
         tuned, _ = B.bmmc_autotune(n, w, method, stream, 3)
+    if tuned:
         opts = dict(tuned)
-        opts["method"] = method
+    passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
 
     def step():
         B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
@@ -384,17 +423,11 @@ def main():
     B.bmmc_copy_ex(x, y, nbytes, 4, 0, stream)
     dev_copy = gbps(nbytes, copy_ms)
     extras = {"device_copy": copy_how}
-    if method == B.METHOD_AUTO:
+    if method == B.METHOD_AUTO and not args.no_extras:
         naive_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, c, w, stream), 10, 2, stream)
         extras["naive_GBps"] = round(gbps(nbytes, naive_ms), 1)
-        one_opts = {"method": B.METHOD_ONEPASS}
-        if not args.no_tune:
-            one_opts, _ = B.bmmc_autotune(n, w, B.METHOD_ONEPASS, stream, 3)
-            one_opts["method"] = B.METHOD_ONEPASS
-        one_ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, one_opts, stream), 20, 3, stream)
-        extras["onepass_GBps"] = round(gbps(nbytes, one_ms), 1)
-        extras["onepass_pct_of_device_copy"] = round(100.0 * gbps(nbytes, one_ms) / dev_copy, 2)
-        extras["onepass_pct_of_hbm_peak"] = round(100.0 * gbps(nbytes, one_ms) / HBM_PEAK_GBPS, 2)
+        extras["paper_two_pass"] = paper_two_pass(x, y, n, rows, c, w, stream, dev_copy,
+                                                  tune=not (args.no_tune or args.options_from))
 
     # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
     dname, d = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
@@ -427,10 +460,10 @@ def main():
     }
     del x, y
     torch.cuda.empty_cache()
-    if not args.no_batched:
+    if not args.no_batched and not args.no_extras:
         line["batched"] = bench_batched()
         torch.cuda.empty_cache()
-    if not args.no_served:
+    if not args.no_served and not args.no_extras:
         line["served"] = bench_served(args.served_rate, args.served_seconds)
         torch.cuda.empty_cache()
     if not args.no_cpu:

@@ -57,15 +57,20 @@ typedef enum {
     BMMC_ERR_BUSY = -9      /* request not finished yet (non-blocking poll) */
 } bmmc_status;
 
-/* How a permutation is carried out. */
+/* How a permutation is carried out.  Every method gives the same result. */
 typedef enum {
+    /* One HBM round trip for every A: one tiled pass (Section 5.1) when A is
+       tiled or the whole array fits one tile, otherwise one pass whose tile is
+       the span of the low run_in input bits and of the inputs that reach the
+       low run_out output bits (not in the paper; both sides still move runs
+       of whole cache lines).  A tuned call may pick BMMC_METHOD_TILED where it
+       measured faster. */
+    BMMC_METHOD_AUTO = 0,
     /* The paper's scheme (Sections 5.1-5.2): one LDS-staged pass when A is
        tiled or the whole array fits one tile, otherwise the factorization
        A = (U.R)(R.L.P) and two passes through a library-owned scratch array. */
-    BMMC_METHOD_AUTO = 0,
-    BMMC_METHOD_TILED = 1,   /* same as AUTO */
-    /* One pass for any A: the tile is the span of the low t input bits and of
-       the inputs that reach the low t output bits (not in the paper). */
+    BMMC_METHOD_TILED = 1,
+    /* The general one-pass tile above, also for tiled A. */
     BMMC_METHOD_ONEPASS = 2,
     /* Lower bound: one lane per element, coalesced reads, scattered writes
        (the paper's naive kernels, Appendix). */
@@ -227,10 +232,11 @@ int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint6
 
 /* ------------------------------------------------------- device calls */
 
-/* The permutation out[A.x XOR c] = in[x] by the paper's scheme (one or two
-   LDS-staged tiled passes).  Plans are cached by (A, c, n, elem_bytes);
-   two-pass plans use a scratch array of 2^n * elem_bytes owned by the
-   library (kept per device and stream, grown on demand).
+/* The permutation out[A.x XOR c] = in[x] (Section 2), by BMMC_METHOD_AUTO or
+   by the options bmmc_autotune stored for (n, elem_bytes).  Plans are cached
+   by (A, c, n, elem_bytes, options); two-pass plans (BMMC_METHOD_TILED) use a
+   scratch array of 2^n * elem_bytes owned by the library (kept per device
+   and stream, grown on demand).
    Errors: _ARG, _SINGULAR, _RANGE, _ALIAS, _NOMEM, _HIP. */
 int bmmc_permute(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
                  int elem_bytes, void* stream);

@@ -281,11 +281,13 @@ int batch_validate(const bmmc_desc_t* descs, int count) {
 
 int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out) {
     PlanOptions po;
-    po.method = (method == BMMC_METHOD_ONEPASS) ? kMethodOnePass : kMethodAuto;
-    po.shape = default_shape(d.elem_bytes);
+    po.method = (method == BMMC_METHOD_ONEPASS || method == BMMC_METHOD_TILED) ? method : kMethodAuto;
     if (d.elem_bytes >= 4) {
+        // the batched kernel's one shape
+        po.shape = default_shape(d.elem_bytes);
         po.shape.nt = batched_threads();
         po.shape.iters = batched_iters();
+        po.shape_given = true;
     }
     int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, po, &out->plan);
     if (st != BMMC_OK) return st;

@@ -147,6 +147,25 @@ KernelShape default_shape(int w) {
 
 int default_t(const KernelShape& ks) { return ks.D() / 2; }
 
+KernelShape general_shape(int w) {
+    KernelShape k = default_shape(w);
+    if (w == 4) k.iters = 8;  // D = 13
+    return k;
+}
+
+void general_runs(const KernelShape& ks, int* a, int* b) {
+    const int D = ks.D();
+    // measured on 2^26..2^28-element random matrices: the longer run on the
+    // write side for 4-byte elements, on the read side for 8-byte elements
+    if (ks.w == 8 && D == 12) {
+        *a = 7;
+        *b = 5;
+        return;
+    }
+    *b = (D + 1) / 2;
+    *a = D - *b;
+}
+
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
                uint64_t seed, PassPlan* p, int tb_mix, int iter_mix) {
     const int n = T.n;
@@ -370,7 +389,8 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
     p->A = A;
     p->c = c;
     p->method = opt.method;
-    p->shape = (opt.shape.w == w) ? opt.shape : default_shape(w);
+    p->shape = opt.shape_given ? opt.shape : default_shape(w);
+    if (p->shape.w != w) return BMMC_ERR_ARG;
     const KernelShape& ks = p->shape;
     if (n == 0) return BMMC_OK;  // one element: plain copy
     if (opt.method == kMethodNaive || n < ks.lv()) {
@@ -386,15 +406,29 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
     p->t = t;
     uint64_t seed = 0x243F6A8885A308D3ull ^ ((uint64_t)n << 32) ^ (uint64_t)w;
     int st;
-    if (opt.method == kMethodOnePass || n <= D || is_tiled(A, b)) {
-        // One pass: the whole array fits a tile, A is tiled (its inputs that
-        // reach the low b output bits are index bits), or the caller asked
-        // for a general tile.
-        // Auto: mixed tile selection for tiled matrices larger than a tile
-        // (their tiles' rows sit at power-of-two strides; mixing which tiles
-        // run together spreads the concurrent accesses).
-        const int mix = opt.tb_mix >= 0 ? opt.tb_mix : (n > D && opt.method != kMethodOnePass ? 1 : 0);
+    if (opt.method != kMethodOnePass && (n <= D || is_tiled(A, b))) {
+        // One tiled pass: the whole array fits a tile, or A is tiled (its
+        // inputs that reach the low b output bits are index bits).  Tiles of
+        // a tiled matrix larger than a tile have their rows at power-of-two
+        // strides; by default, mixing which tiles run together spreads the
+        // concurrent accesses.
+        const int mix = opt.tb_mix >= 0 ? opt.tb_mix : (n > D ? 1 : 0);
         st = build_pass(A, c, a, b, ks, opt.swizzle, seed, &p->pass[0], mix, opt.iter_mix);
+        if (st != BMMC_OK) return st;
+        p->npass = 1;
+        return BMMC_OK;
+    }
+    if (opt.method == kMethodOnePass || opt.method == kMethodAuto) {
+        // One pass with a general tile: the span of the low a input bits and
+        // of the inputs that reach the low b output bits.  With a + b <= D it
+        // fits one tile for every A.
+        if (!opt.shape_given) p->shape = general_shape(w);
+        const KernelShape& gs = p->shape;
+        int ga = a, gb = b;
+        if (opt.t <= 0 && opt.a <= 0 && opt.b <= 0) general_runs(gs, &ga, &gb);
+        if (ga < gs.lv() || gb < gs.lv() || ga > gs.D() || gb > gs.D()) return BMMC_ERR_RANGE;
+        st = build_pass(A, c, ga, gb, gs, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0,
+                        opt.iter_mix);
         if (st != BMMC_OK) return st;
         p->npass = 1;
         return BMMC_OK;

@@ -9,8 +9,8 @@
 namespace bmmc {
 
 enum Method : int {
-    kMethodAuto = 0,     // the paper's scheme: one tiled pass if A is tiled, else two
-    kMethodTiled = 1,    // same as auto
+    kMethodAuto = 0,     // one tiled pass if A is tiled, else one pass with a general tile
+    kMethodTiled = 1,    // the paper's scheme: one tiled pass if A is tiled, else two
     kMethodOnePass = 2,  // one pass with a general (non-coordinate) tile
     kMethodNaive = 3,    // one element per lane, scattered writes
 };
@@ -53,7 +53,8 @@ struct PlanOptions {
     int swizzle = 1;  // 0: plain layout, 1: conflict-avoiding XOR layout
     int tb_mix = -1;  // 1: tile-selecting vectors are XOR combinations of index bits; -1: auto
     int iter_mix = 0; // 1: iteration vectors are XOR combinations of index bits
-    KernelShape shape;
+    bool shape_given = false;  // false: the default shape for the width and kind of tile
+    KernelShape shape;         // used when shape_given
 };
 
 struct Plan {
@@ -88,6 +89,10 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
 // Default kernel shape and run bits for an element width.
 KernelShape default_shape(int w);
 int default_t(const KernelShape& ks);
+// Defaults of the general one-pass tile: its shape, and the read-run and
+// write-run bits (a, b) with a + b <= D, so that any A fits one tile.
+KernelShape general_shape(int w);
+void general_runs(const KernelShape& ks, int* a, int* b);
 
 // Bank-conflict residue of an LDS layout for the lanes of one wave
 // (sum over read side / write side and 32 / 64 bank models of the rank

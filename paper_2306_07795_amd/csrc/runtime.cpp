@@ -86,8 +86,8 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
     key.t = o.t;
     key.a = o.a;
     key.b = o.b;
-    key.nt = o.shape.nt;
-    key.iters = o.shape.iters;
+    key.nt = o.shape_given ? o.shape.nt : 0;
+    key.iters = o.shape_given ? o.shape.iters : 0;
     key.swizzle = o.swizzle;
     key.tb_mix = o.tb_mix;
     key.iter_mix = o.iter_mix;
@@ -168,19 +168,18 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     p.shape = default_shape(w);
     if (!o) return p;
     p.method = o->method;
-    if (o->method == BMMC_METHOD_ONEPASS && o->threads == 0 && o->iters == 0 && o->t == 0 &&
-        o->run_in == 0 && o->run_out == 0) {
-        // measured defaults for the general one-pass tile: a 2^13 tile with
-        // longer runs on one side
-        if (w == 4) { p.shape.iters = 8; p.a = 6; p.b = 7; }
-        if (w == 8) { p.shape.iters = 8; p.a = 7; p.b = 5; }
-    }
     if (o->t) p.t = o->t;
     if (o->run_in) p.a = o->run_in;
     if (o->run_out) p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
     if (o->tile_order) p.tb_mix = (o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1);
     p.iter_mix = (o->tile_order >> 3) & 1;
+    if (o->threads > 0 || o->iters > 0) {
+        // a shape given in part takes the rest from the default of its kind
+        const bool general = o->method == BMMC_METHOD_ONEPASS || o->method == BMMC_METHOD_AUTO;
+        p.shape = general ? general_shape(w) : default_shape(w);
+        p.shape_given = true;
+    }
     if (o->threads > 0) p.shape.nt = o->threads;
     if (o->iters > 0) p.shape.iters = o->iters;
     return p;
@@ -325,7 +324,7 @@ int bmmc_factorize_t(const uint64_t* A_rows, uint64_t c, int n, int t, int elem_
     if (!plan_out) return set_error(BMMC_ERR_ARG, "plan_out is NULL");
     PlanOptions o;
     int w = elem_bytes > 0 ? elem_bytes : 4;
-    o.shape = default_shape(w);
+    o.method = kMethodTiled;  // the factorization of Section 5
     o.t = t;
     Plan p;
     int st = make_plan(A_rows, c, n, w, o, &p);

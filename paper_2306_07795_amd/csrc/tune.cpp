@@ -211,33 +211,36 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         const int runs[][2] = {{h, h}, {D - h, h}, {h, D - h}, {h + 1, D - h - 1}, {D - h - 1, h + 1}};
         for (auto& ab : runs) {
             if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
-            for (int hints : {4, 2, 3}) {
-                for (int order : {4, 2, 10}) {
-                    for (int g = 0; g < 2; g++) {
-                        bmmc_options_t o;
-                        std::memset(&o, 0, sizeof(o));
-                        o.method = method;
-                        o.t = ab[0] < ab[1] ? ab[0] : ab[1];
-                        o.run_in = ab[0];
-                        o.run_out = ab[1];
-                        o.threads = ks.nt;
-                        o.iters = ks.iters;
-                        o.swizzle = 1;
-                        o.hints = hints;
-                        o.tile_order = order;
-                        o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
-                        st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                        if (st != BMMC_OK) continue;  // shape does not fit this size
-                        hipEventRecord(tm.a, stream);
-                        for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                        hipEventRecord(tm.b, stream);
-                        hipEventSynchronize(tm.b);
-                        float ms = 0;
-                        hipEventElapsedTime(&ms, tm.a, tm.b);
-                        const double per = ms / reps;
-                        if (per < best) {
-                            best = per;
-                            bo = o;
+            for (int m = 0; m < (method == BMMC_METHOD_AUTO ? 2 : 1); m++) {
+                for (int hints : {4, 2, 3}) {
+                    for (int order : {4, 2, 10}) {
+                        for (int g = 0; g < 2; g++) {
+                            bmmc_options_t o;
+                            std::memset(&o, 0, sizeof(o));
+                            // auto also tries the paper's two-pass scheme
+                            o.method = m == 0 ? method : BMMC_METHOD_TILED;
+                            o.t = ab[0] < ab[1] ? ab[0] : ab[1];
+                            o.run_in = ab[0];
+                            o.run_out = ab[1];
+                            o.threads = ks.nt;
+                            o.iters = ks.iters;
+                            o.swizzle = 1;
+                            o.hints = hints;
+                            o.tile_order = order;
+                            o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
+                            st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                            if (st != BMMC_OK) continue;  // shape does not fit this size
+                            hipEventRecord(tm.a, stream);
+                            for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                            hipEventRecord(tm.b, stream);
+                            hipEventSynchronize(tm.b);
+                            float ms = 0;
+                            hipEventElapsedTime(&ms, tm.a, tm.b);
+                            const double per = ms / reps;
+                            if (per < best) {
+                                best = per;
+                                bo = o;
+                            }
                         }
                     }
                 }
@@ -277,30 +280,33 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     bmmc_batch_options_t bo;
     std::memset(&bo, 0, sizeof(bo));
     Timer tm;
-    for (int chunk : kChunks) {
-        for (int order = 0; order < 2; order++) {
-            for (int g = 1; g <= 2; g++) {
-                bmmc_batch_options_t o;
-                std::memset(&o, 0, sizeof(o));
-                o.chunk_tiles = chunk;
-                o.order = order;
-                o.workgroups = ds->cu_count * occ * g / 2;
-                // time graph replays of a resident batch: device time only
-                void* pb = nullptr;
-                st = bmmc_batch_create(descs, count, &o, &pb);
-                if (st != BMMC_OK) return st;
-                bmmc_batch_launch(pb, stream);  // warm-up
-                hipEventRecord(tm.a, stream);
-                for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
-                hipEventRecord(tm.b, stream);
-                hipEventSynchronize(tm.b);
-                bmmc_batch_destroy(pb);
-                float ms = 0;
-                hipEventElapsedTime(&ms, tm.a, tm.b);
-                const double per = ms / reps;
-                if (per < best) {
-                    best = per;
-                    bo = o;
+    for (int method : {BMMC_METHOD_AUTO, BMMC_METHOD_TILED}) {
+        for (int chunk : kChunks) {
+            for (int order = 0; order < 2; order++) {
+                for (int g = 1; g <= 2; g++) {
+                    bmmc_batch_options_t o;
+                    std::memset(&o, 0, sizeof(o));
+                    o.method = method;
+                    o.chunk_tiles = chunk;
+                    o.order = order;
+                    o.workgroups = ds->cu_count * occ * g / 2;
+                    // time graph replays of a resident batch: device time only
+                    void* pb = nullptr;
+                    st = bmmc_batch_create(descs, count, &o, &pb);
+                    if (st != BMMC_OK) return st;
+                    bmmc_batch_launch(pb, stream);  // warm-up
+                    hipEventRecord(tm.a, stream);
+                    for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
+                    hipEventRecord(tm.b, stream);
+                    hipEventSynchronize(tm.b);
+                    bmmc_batch_destroy(pb);
+                    float ms = 0;
+                    hipEventElapsedTime(&ms, tm.a, tm.b);
+                    const double per = ms / reps;
+                    if (per < best) {
+                        best = per;
+                        bo = o;
+                    }
                 }
             }
         }

@@ -37,17 +37,18 @@ def check_all(arrays):
         assert np.array_equal(got, want), f"array {k}: n={ar['n']} w={ar['w']}"
 
 
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 @pytest.mark.parametrize("use_graph", [1, -1])
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("hints", [0, 3, 4])
-def test_batched_mixed_sizes_and_widths(order, use_graph, hints):
+def test_batched_mixed_sizes_and_widths(order, use_graph, hints, method):
     rng = np.random.default_rng(order)
     sizes = [int(v) for v in rng.integers(0, 19, size=48)]
     widths = [int(v) for v in rng.choice([4, 8, 16, 1, 2], size=48)]
     arrays = make_batch(sizes, widths, 3 + order)
     B.bmmc_permute_batched(items(arrays), G.stream(),
                            {"order": order, "use_graph": use_graph, "chunk_tiles": 1 + 2 * order,
-                            "hints": hints})
+                            "hints": hints, "method": method})
     G.sync()
     check_all(arrays)
 
@@ -85,7 +86,8 @@ def test_graph_replays_with_fresh_data():
         check_all(arrays)
 
 
-def test_batch_of_1024_like_the_workload():
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_batch_of_1024_like_the_workload(method):
     """1024 arrays, n uniform in [10, 22], int32, each with its own A and c
     (the batched workload's shape); every array checked on sampled outputs
     and the smallest hundred in full."""
@@ -96,7 +98,7 @@ def test_batch_of_1024_like_the_workload():
         a = gen.data(n, 4, k)
         arrays.append({"n": n, "w": 4, "rows": rows, "c": c, "a": a,
                        "x": G.to_device(a), "y": G.empty_like_bytes(a)})
-    B.bmmc_permute_batched(items(arrays), G.stream())
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"method": method})
     G.sync()
     rng = np.random.default_rng(0)
     order = sorted(range(len(arrays)), key=lambda k: arrays[k]["n"])
@@ -148,10 +150,11 @@ def test_autotune_batched_small():
 
 # ------------------------------------------------------------------ server
 
-def test_server_mix_equals_alone_equals_oracle():
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_server_mix_equals_alone_equals_oracle(method):
     reqs = gen.poisson_requests(60, 20000.0, 7, n_lo=8, n_hi=20)
     pool = {}
-    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True)
+    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True, method=method)
     try:
         t0 = B.bmmc_server_now_ns() + 2_000_000
         tickets = []
@@ -181,7 +184,7 @@ def test_server_mix_equals_alone_equals_oracle():
     finally:
         B.bmmc_server_destroy(srv)
     # the same requests alone, one server each time
-    srv = B.bmmc_server_create(1 << 28, streams=1, own_outputs=True)
+    srv = B.bmmc_server_create(1 << 28, streams=1, own_outputs=True, method=method)
     try:
         for r in reqs[:12]:
             rows, c, a, x = pool[r["id"]]
@@ -196,11 +199,13 @@ def test_server_mix_equals_alone_equals_oracle():
         B.bmmc_server_destroy(srv)
 
 
-def test_server_budget_admission_and_caller_outputs():
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_server_budget_admission_and_caller_outputs(method):
     """A budget that admits one large request at a time still completes all,
     in order; outputs provided by the caller."""
     n, w = 20, 4
-    srv = B.bmmc_server_create(3 * (1 << n) * w + (1 << 20), streams=2, own_outputs=False)
+    srv = B.bmmc_server_create(3 * (1 << n) * w + (1 << 20), streams=2, own_outputs=False,
+                               method=method)
     try:
         work = []
         for k in range(6):
@@ -223,14 +228,15 @@ def test_server_budget_admission_and_caller_outputs():
         B.bmmc_server_destroy(srv)
 
 
-def test_prepared_batch_replays():
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_prepared_batch_replays(method):
     """A resident batch (plans, table, scratch and graph made once) replayed
     with fresh inputs each time; every array checked each time."""
     rng = np.random.default_rng(31)
     sizes = [int(v) for v in rng.integers(0, 21, size=40)]
     widths = [int(v) for v in rng.choice([4, 8, 16, 2], size=40)]
     arrays = make_batch(sizes, widths, 31)
-    pb = B.bmmc_batch_create(items(arrays))
+    pb = B.bmmc_batch_create(items(arrays), {"method": method})
     try:
         for rep in range(3):
             for k, ar in enumerate(arrays):

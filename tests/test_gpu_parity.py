@@ -53,20 +53,24 @@ def test_bit_reversal_2p20_int32_full():
     assert np.array_equal(run(n, rows, 0, 4, a), O.permute(a, n, rows, 0))
 
 
-def test_random_2p26_int32_full():
-    """Random BMMC on 2^26 int32, seed 0: two tiled passes, full comparison."""
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_random_2p26_int32_full(method):
+    """Random BMMC on 2^26 int32, seed 0, full comparison: one general-tile
+    pass (auto) and the paper's two tiled passes."""
     n = 26
     rows, c = gen.random_bmmc(n, 0)
-    assert B.bmmc_factorize(rows, c, n).nfactors == 2
+    opts = {"method": method}
+    assert B.bmmc_plan_ex(rows, c, n, 4, opts).nfactors == (1 if method == B.METHOD_AUTO else 2)
     a = gen.data(n, 4, 0)
-    got = run(n, rows, c, 4, a)
+    got = run(n, rows, c, 4, a, fn="ex", opts=opts)
     assert np.array_equal(got, O.permute(a, n, rows, c))
 
 
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 @pytest.mark.parametrize("w", [4, 8])
 @pytest.mark.parametrize("kind", ["random", "bitrev", "swap", "bpc", "cyclic", "reverse", "identity"])
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 9, 12, 13, 15, 18])
-def test_small_sizes(kind, n, w):
+def test_small_sizes(kind, n, w, method):
     s = 31 * n + w
     rows, c = {
         "random": lambda: gen.random_bmmc(n, s),
@@ -77,7 +81,7 @@ def test_small_sizes(kind, n, w):
         "reverse": lambda: (gen.identity_rows(n), (1 << n) - 1),
         "identity": lambda: (gen.identity_rows(n), 0),
     }[kind]()
-    check(n, rows, c, w)
+    check(n, rows, c, w, fn="ex", opts={"method": method})
 
 
 @pytest.mark.parametrize("w", [1, 2, 16])
@@ -105,11 +109,13 @@ def test_onepass_method(n, w):
     {"threads": 512, "iters": 4}, {"threads": 1024, "iters": 2}, {"threads": 256, "iters": 8},
     {"threads": 256, "iters": 2}, {"threads": 1024, "iters": 4}, {"t": 5},
     {"swizzle": -1}, {"grid": 64}, {"grid": 1}, {"threads": 256, "iters": 16, "t": 7},
+    {"run_in": 7, "run_out": 6, "threads": 512, "iters": 8, "tile_order": 2, "hints": 3},
 ])
-def test_shapes_and_grids(opts):
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_shapes_and_grids(opts, method):
     n = 19
     rows, c = gen.random_bmmc(n, 99)
-    check(n, rows, c, 4, fn="ex", opts=opts)
+    check(n, rows, c, 4, fn="ex", opts={**opts, "method": method})
 
 
 @pytest.mark.parametrize("opts", [{"threads": 256, "iters": 4}, {"threads": 512, "iters": 8},
@@ -138,11 +144,12 @@ def sampled_check(n, rows, c, w, got, a, count=1 << 16, seed=0):
 
 
 @pytest.mark.parametrize("case", ["random28_i32", "random27_i64", "bitrev28_i32", "swap28_i32",
-                                  "swap27_i64"])
+                                  "swap27_i64", "random28_i32_tiled", "random27_i64_tiled"])
 def test_full_size_sweep_sampled(case):
-    """The 1 GiB sweep arrays in the benchmark's launch configuration, checked
-    on 65536 sampled outputs computed one by one by the oracle."""
-    n, w = (28, 4) if case.endswith("i32") else (27, 8)
+    """The 1 GiB sweep arrays in the benchmark's launch configuration (and in
+    the paper's two-pass scheme), checked on 65536 sampled outputs computed
+    one by one by the oracle."""
+    n, w = (28, 4) if "i32" in case else (27, 8)
     if case.startswith("random"):
         rows, c = gen.random_bmmc(n, 1)
     elif case.startswith("bitrev"):
@@ -150,7 +157,8 @@ def test_full_size_sweep_sampled(case):
     else:
         rows, c = gen.block_swap_rows(n, n // 2), 0
     a = gen.data(n, w, 1)
-    got = run(n, rows, c, w, a)
+    got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_TILED}) if case.endswith("tiled") \
+        else run(n, rows, c, w, a)
     sampled_check(n, rows, c, w, got, a)
 
 
@@ -177,16 +185,17 @@ def test_same_result_on_side_stream():
     assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
 
 
-def test_profile_reports_launches():
+@pytest.mark.parametrize("method,per_call", [(B.METHOD_AUTO, 1), (B.METHOD_TILED, 2)])
+def test_profile_reports_launches(method, per_call):
     n = 20
     rows, c = gen.random_bmmc(n, 9)
     a = gen.data(n, 4, 2)
     x, y = G.to_device(a), G.empty_like_bytes(a)
     B.bmmc_profile_begin()
     for _ in range(3):
-        B.bmmc_permute(x, y, n, rows, c, 4, G.stream())
+        B.bmmc_permute_ex(x, y, n, rows, c, 4, {"method": method}, G.stream())
     st = B.bmmc_profile_end()
-    assert sum(v["launches"] for v in st.values()) == 6
+    assert sum(v["launches"] for v in st.values()) == 3 * per_call
     assert all(v["total_ms"] > 0 for v in st.values())
 
 

@@ -271,12 +271,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("n", [3, 8, 12, 13, 16, 18])
 @pytest.mark.parametrize("w", [4, 8])
-def test_emulation_matches_oracle(name, mk, n, w):
+def test_emulation_matches_oracle(name, mk, n, w, method):
     rows, c = mk(n, n * 13 + w)
-    st = emulate_check(n, rows, c, w)
+    st = emulate_check(n, rows, c, w, {"method": method})
     if n >= 8:
         # every wave access is one run of whole lines, and conflict-free LDS
         assert st["read_lines"] == st["read_lines_min"]
@@ -319,12 +320,29 @@ def test_emulation_shapes(opts):
         assert st["lds_conflicts64"] == 0
 
 
+def test_auto_takes_one_pass_and_tiled_the_papers_two():
+    """Auto: one pass for every A (a tiled pass, or one general tile);
+    the tiled method: the paper's factorization, two passes unless A is tiled."""
+    for n, w in [(14, 4), (20, 4), (26, 4), (27, 8), (24, 16), (20, 1), (20, 2)]:
+        rows, c = gen.random_bmmc(n, n + w)
+        auto = B.bmmc_plan_ex(rows, c, n, w, None)
+        assert auto.nfactors == 1 and auto.coordinate[0] == 0
+        tiled = B.bmmc_plan_ex(rows, c, n, w, {"method": B.METHOD_TILED})
+        assert tiled.nfactors == 2 and tiled.coordinate[0] == 1 and tiled.coordinate[1] == 1
+        assert B.bmmc_factorize(rows, c, n).nfactors == 2
+        br = gen.bit_reversal_rows(n)
+        for m in (B.METHOD_AUTO, B.METHOD_TILED):
+            p = B.bmmc_plan_ex(br, 0, n, w, {"method": m})
+            assert p.nfactors == 1 and p.coordinate[0] == 1
+
+
 def test_emulation_iota_two_pass_n20():
     n = 20
     rows, c = gen.random_bmmc(n, 20)
     a = gen.iota(n, 4)
     out = np.zeros_like(a)
-    B.bmmc_emulate(a, out, n, rows, c, 4)
+    st = B.bmmc_emulate(a, out, n, rows, c, 4, {"method": B.METHOD_TILED})
+    assert st["tiles"] == 2 * 2 ** (n - 12)
     ys = O.index_map(rows, c, n)
     assert np.array_equal(out[ys.astype(np.int64)], a)
 
