@@ -179,3 +179,16 @@ def matvec(a: np.ndarray, x: int) -> int:
             s ^= int(a[i, j]) & ((x >> j) & 1)
         y |= s << i
     return y
+
+
+def sort_keys(keys: np.ndarray, signed: bool = True) -> np.ndarray:
+    """Section 7.1: the even/odd merge sort written with parm (a balanced
+    periodic merger of V-shaped columns) sorts its input into ascending
+    order, so its result is the sorted keys; a library sort is that step.
+    keys: 4-byte keys compared as int32 (signed) or uint32; returned with the
+    input's dtype."""
+    a = np.ascontiguousarray(keys)
+    if a.dtype.itemsize != 4:
+        raise ValueError("4-byte keys expected")
+    v = a.view(np.int32 if signed else np.uint32)
+    return np.sort(v, kind="stable").view(a.dtype)

@@ -297,3 +297,71 @@ def test_every_bpc_is_tiled(n, seed):
         ok, cols = O.is_tiled(m, t)
         assert ok
         assert cols == sum(1 << j for j in range(n) if p[j] < t)
+
+
+# ------------------------------------------- sorting network (Section 7.1)
+
+def _parm_py(mask, f, xs):
+    """parm by its definition: sub-array of index i = parity of i & mask,
+    order kept inside each sub-array, f applied to each, stitched back."""
+    sub = [bin(i & mask).count("1") & 1 for i in range(len(xs))]
+    parts = [[x for x, s in zip(xs, sub) if s == k] for k in (0, 1)]
+    done = [iter(f(p)) for p in parts]
+    return [next(done[s]) for s in sub]
+
+
+def _vcolumn_py(n, xs):
+    if n == 0:
+        return xs
+    if n == 1:
+        return xs if xs[0] <= xs[1] else [xs[1], xs[0]]
+    return _parm_py(3, lambda s: _vcolumn_py(n - 1, s), xs)
+
+
+def _merge_py(n, xs):
+    if n == 0:
+        return xs
+    ys = _vcolumn_py(n, xs)
+    return _parm_py(1 << (n - 1), lambda s: _merge_py(n - 1, s), ys)
+
+
+def _sortnet_py(n, xs):
+    if n == 0:
+        return xs
+    ys = _parm_py(1, lambda s: _sortnet_py(n - 1, s), xs)
+    return _merge_py(n, ys)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_papers_network_sorts_every_zero_one_input(n):
+    """The 0-1 principle over every 0-1 input: the network of Section 7.1,
+    written out by its recursion, gives the oracle's sorted keys."""
+    for bits in itertools.product([0, 1], repeat=1 << n):
+        a = np.array(bits, dtype=np.int32)
+        assert np.array_equal(np.array(_sortnet_py(n, list(bits)), dtype=np.int32), O.sort_keys(a))
+
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (6, 1), (7, 2)])
+def test_papers_network_on_integers_with_duplicates(n, seed):
+    a = np.random.default_rng(seed).integers(-20, 20, size=1 << n).astype(np.int32)
+    assert np.array_equal(np.array(_sortnet_py(n, a.tolist()), dtype=np.int32), O.sort_keys(a))
+
+
+@pytest.mark.parametrize("signed", [True, False])
+@pytest.mark.parametrize("n,seed", [(0, 0), (4, 1), (12, 2), (16, 3)])
+def test_sort_oracle_is_an_ordered_rearrangement(n, seed, signed):
+    """Ascending in the key order and the same multiset of keys: the unique
+    result of sorting."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(-(1 << 31), 1 << 31, size=1 << n, dtype=np.int64).astype(np.int32)
+    a[: len(a) // 4] = a[0]  # duplicates
+    out = O.sort_keys(a, signed)
+    k = out.view(np.int32 if signed else np.uint32).astype(np.int64)
+    assert np.all(k[1:] >= k[:-1])
+    va, ca = np.unique(a, return_counts=True)
+    vo, co = np.unique(out, return_counts=True)
+    assert np.array_equal(va, vo) and np.array_equal(ca, co)
+    if not signed and n >= 4:
+        # negative int32 keys are large unsigned keys: they come last
+        neg = np.nonzero(out < 0)[0]
+        assert len(neg) == 0 or neg[0] == len(out) - len(neg)
