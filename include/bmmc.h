@@ -223,6 +223,43 @@ int bmmc_parm_matrix(uint64_t mask, int n, uint64_t* rows_out, uint64_t* inv_row
 int bmmc_permute_seq(const void* in, void* out, int n, int count, const uint64_t* A_rows_seq,
                      const uint64_t* c_seq, int elem_bytes, void* stream);
 
+/* ----------------------------------------- sorting network (Section 7.1) */
+
+/* Key order of the sorting network. */
+typedef enum {
+    BMMC_KEY_I32 = 0, /* 4-byte keys compared as signed 32-bit integers */
+    BMMC_KEY_U32 = 1  /* 4-byte keys compared as unsigned 32-bit integers */
+} bmmc_key_type;
+
+/* How the network runs. */
+typedef enum {
+    /* parm compiled to BMMCs (Section 7.2) and fused (Section 3): each of the
+       n(n+1)/2 compare-exchange columns is one LDS-staged pass whose reads
+       and writes are coalesced, the compare-exchange done as the pass stores;
+       plus one final pass. */
+    BMMC_SORTNET_PASSES = 0,
+    /* every column in place at the keys' own positions (no permutations;
+       accesses as scattered as the column's pairs): the uncompiled form */
+    BMMC_SORTNET_DIRECT = 1
+} bmmc_sortnet_method;
+
+/* The network as the compiled sequence M_0, C, M_1, C, ..., C, M_S of
+   S = n(n+1)/2 compare-exchange columns C between fused BMMCs (linear, c = 0),
+   where C orders each pair (2k, 2k+1) of the index space it sees, smaller key
+   first, and M_S ... M_0 = I.  Writes *count_out = S + 1 and, when rows_out
+   is not NULL, matrix s to rows_out[s*n .. s*n + n-1] (room for max_matrices
+   matrices).  Host only.  Errors: _RANGE (n, or too little room),
+   _INTERNAL. */
+int bmmc_sortnet_stages(int n, uint64_t* rows_out, int max_matrices, int* count_out);
+
+/* Sort 2^n 4-byte keys ascending with the sorting network of Section 7.1
+   (even/odd merge sort, balanced periodic merger, written with parm):
+   out = the keys of in in ascending key_type order.  in and out are distinct
+   16-byte aligned device buffers of 4 * 2^n bytes; BMMC_SORTNET_PASSES uses
+   the library's per-stream scratch array of the same size.  Asynchronous on
+   `stream`.  Errors: _ARG, _RANGE, _ALIAS, _NOMEM, _HIP, _INTERNAL. */
+int bmmc_sortnet(const void* in, void* out, int n, int key_type, int method, void* stream);
+
 /* Host emulation of the tiled kernels' address arithmetic, for tests: runs
    the same plan, tile by tile and lane by lane, on host memory (in/out are
    HOST pointers here) and counts coalescing, LDS bank conflicts and LDS
@@ -288,14 +325,23 @@ int bmmc_batch_destroy(void* handle);
 
 /* ------------------------------------------------------------- autotuner */
 
-/* Time the available tile shapes (threads x iterations), run widths t and
-   grid sizes on a random permutation of 2^n elements of elem_bytes bytes with
-   `method`, `reps` timed runs each, on `stream` (synchronizes it).  The
-   fastest is cached for (n, elem_bytes, method) and used by later calls that
-   pass no options; it is also returned.  Allocates two temporary buffers of
-   2^n * elem_bytes.  Errors: _RANGE, _ARG, _NOMEM, _HIP. */
+/* Time the available tile shapes (threads x iterations), run widths, cache
+   hints, tile orders and grid sizes (with BMMC_METHOD_AUTO also the two-pass
+   scheme) on 2^n elements of elem_bytes bytes, `reps` timed runs each, on
+   `stream` (synchronizes it), for two classes of matrices: a random matrix
+   (class 0: not tiled) and a random bit permutation (class 1: tiled).  The
+   fastest of each class is cached for (n, elem_bytes, method, class) and used
+   by later calls that pass no options, by the class of their matrix; class
+   0's is also returned.  Allocates two temporary buffers of 2^n * elem_bytes.
+   Errors: _RANGE, _ARG, _NOMEM, _HIP. */
 int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
                   bmmc_options_t* best_out, double* best_ms);
+
+/* The tuned options of `method` for this matrix's class: returns 1 and fills
+   *opts_out when the cache holds an entry, else 0.  With BMMC_METHOD_AUTO
+   these are the options a call without options uses (else the library
+   defaults).  Host only.  Errors: _ARG, _RANGE. */
+int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows, bmmc_options_t* opts_out);
 
 /* Time chunk size, queue order and persistent grid size of the batched
    kernel on this very batch (it runs the batch 1 + reps times per candidate);

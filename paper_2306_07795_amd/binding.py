@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libbmmc.so")
 
 MAX_BITS = 32
 METHOD_AUTO, METHOD_TILED, METHOD_ONEPASS, METHOD_NAIVE = 0, 1, 2, 3
+KEY_I32, KEY_U32 = 0, 1
+SORTNET_PASSES, SORTNET_DIRECT = 0, 1
 
 _c = ctypes
 _u64, _i32, _i64, _vp, _dbl = _c.c_uint64, _c.c_int, _c.c_int64, _c.c_void_p, _c.c_double
@@ -105,6 +107,8 @@ def lib():
         "bmmc_invert": (_i32, [P(_u64), _u64, _i32, P(_u64), P(_u64)]),
         "bmmc_parm_matrix": (_i32, [_u64, _i32, P(_u64), P(_u64)]),
         "bmmc_permute_seq": (_i32, [_vp, _vp, _i32, _i32, P(_u64), P(_u64), _i32, _vp]),
+        "bmmc_sortnet_stages": (_i32, [_i32, P(_u64), _i32, P(_i32)]),
+        "bmmc_sortnet": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp]),
         "bmmc_plan_ex": (_i32, [P(_u64), _u64, _i32, _i32, P(Options), P(Plan)]),
         "bmmc_factorize_ulp": (_i32, [P(_u64), _i32, P(_u64), P(_u64), P(_u64), P(_u64), P(_u64)]),
         "bmmc_permute": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
@@ -122,6 +126,7 @@ def lib():
         "bmmc_autotune_batched": (_i32, [P(Desc), _i32, _vp, _i32, P(BatchOptions), P(_dbl)]),
         "bmmc_autotune": (_i32, [_i32, _i32, _i32, _vp, _i32, P(Options), P(_dbl)]),
         "bmmc_tune_save": (_i32, [_c.c_char_p]),
+        "bmmc_tune_lookup": (_i32, [_i32, _i32, _i32, P(_u64), P(Options)]),
         "bmmc_tune_load": (_i32, [_c.c_char_p]),
         "bmmc_server_create": (_i32, [P(ServerOptions), P(_vp)]),
         "bmmc_server_destroy": (_i32, [_vp]),
@@ -150,7 +155,8 @@ def exported_names():
         "bmmc_profile_begin", "bmmc_profile_end", "bmmc_autotune_batched", "bmmc_autotune",
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
-        "bmmc_server_stats", "bmmc_server_now_ns",
+        "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
+        "bmmc_tune_lookup",
     ]
 
 
@@ -280,6 +286,20 @@ def bmmc_permute_seq(inp, out, n: int, seq, elem_bytes: int, stream=None):
     _check(lib().bmmc_permute_seq(_ptr(inp), _ptr(out), n, count, rows, cs, elem_bytes, _stream(stream)))
 
 
+def bmmc_sortnet_stages(n: int):
+    """The compiled network: list of S + 1 matrices (rows), S = n(n+1)/2
+    compare-exchange columns between them."""
+    count = _c.c_int(0)
+    _check(lib().bmmc_sortnet_stages(n, None, 0, _c.byref(count)))
+    rows = (_u64 * max(count.value * n, 1))()
+    _check(lib().bmmc_sortnet_stages(n, rows, count.value, _c.byref(count)))
+    return [[int(rows[s * n + i]) for i in range(n)] for s in range(count.value)]
+
+
+def bmmc_sortnet(inp, out, n: int, key_type: int = KEY_I32, method: int = SORTNET_PASSES, stream=None):
+    _check(lib().bmmc_sortnet(_ptr(inp), _ptr(out), n, key_type, method, _stream(stream)))
+
+
 def bmmc_emulate(inp, out, n: int, A_rows, c: int, elem_bytes: int, opts=None) -> dict:
     """Host emulation of the kernels; inp/out are host buffers (numpy arrays)."""
     st = EmuStats()
@@ -406,6 +426,18 @@ def bmmc_autotune(n: int, elem_bytes: int, method: int = METHOD_AUTO, stream=Non
     _check(lib().bmmc_autotune(n, elem_bytes, method, _stream(stream), reps, _c.byref(o),
                                _c.byref(ms)))
     return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}, ms.value
+
+
+def bmmc_tune_lookup(n: int, elem_bytes: int, A_rows, method: int = METHOD_AUTO):
+    """The tuned options of `method` for this matrix's class (dict), or None
+    when nothing is tuned for it."""
+    o = Options()
+    r = lib().bmmc_tune_lookup(n, elem_bytes, method, _rows(A_rows, n), _c.byref(o))
+    if r < 0:
+        _check(r)
+    if r == 0:
+        return None
+    return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
 
 
 def bmmc_autotune_batched(items, stream=None, reps: int = 3):

@@ -343,10 +343,13 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
                                            : (uint32_t)(ds->cu_count * batched_occupancy());
     const int hints = resolve_batch_hints(o, moved);
-    LaunchScope ls(ds, stream, "k_batched", moved);
     if (o.use_graph >= 0) {
         st = build_graph(bs, grid, hints);
         if (st != BMMC_OK) return st;
+    }
+    LaunchScope ls(ds, stream, "k_batched", moved);
+    ls.bracket();
+    if (o.use_graph >= 0) {
         e = hipGraphLaunch(bs->exec, stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
@@ -523,6 +526,7 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     for (auto& ba : pb->arrays) any |= !ba.single;
     if (!any) return BMMC_OK;
     LaunchScope ls(ds, stream, "k_batched", pb->moved);
+    ls.bracket();
     hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
                                  : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, stream);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "batch launch");

@@ -154,13 +154,19 @@ LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double
             return;
         }
     }
-    hipEventRecord(pe.start, stream);
     ds->events.push_back(pe);
-    ev = &ds->events.back();
+    ev.start = pe.start;
+    ev.stop = pe.stop;
+}
+
+void LaunchScope::bracket() {
+    if (!ev.start) return;
+    hipEventRecord(ev.start, stream);
+    bracketed = true;
 }
 
 LaunchScope::~LaunchScope() {
-    if (ev) hipEventRecord(ds->events.back().stop, stream);
+    if (bracketed) hipEventRecord(ev.stop, stream);
 }
 
 PlanOptions plan_options(const bmmc_options_t* o, int w) {
@@ -210,7 +216,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
     hipError_t e;
     if (plan.npass == 0) {
         LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
-        e = launch_copy(in, out, bytes, stream);
+        e = launch_copy(in, out, bytes, stream, 4, 0, ls.events());
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
     }
     if (plan.naive) {
@@ -220,7 +226,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         na.c = (uint32_t)plan.c;
         for (int j = 0; j < plan.n; j++) na.col[j] = (uint32_t)plan.A.col(j);
         LaunchScope ls(ds, stream, "k_naive", 2.0 * bytes);
-        e = launch_naive(plan.w, plan.n, in, out, na, stream);
+        e = launch_naive(plan.w, plan.n, in, out, na, stream, ls.events());
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "naive launch");
     }
     const KernelShape& ks = plan.shape;
@@ -241,7 +247,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         kernel_name(name, sizeof(name), plan, hints);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
         e = launch_tiled(plan.w, ks.nt, ks.iters, hints, src, dst, tab, ntiles, grid,
-                         (order & 1) ? (uint32_t)ds->xcds : 0u, stream);
+                         (order & 1) ? (uint32_t)ds->xcds : 0u, stream, ls.events());
         if (e != hipSuccess) return hip_fail(e, "tiled launch");
     }
     return BMMC_OK;
@@ -383,7 +389,7 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     bmmc_options_t tuned;
-    if (!opts && tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, &tuned)) opts = &tuned;
+    if (!opts && tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned)) opts = &tuned;
     PlanOptions po = plan_options(opts, elem_bytes);
     std::shared_ptr<const Plan> plan;
     st = get_plan(ds, A_rows, c, n, elem_bytes, po, &plan);
@@ -415,7 +421,7 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
     if (!ds) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
     LaunchScope ls(ds, (hipStream_t)stream, "k_copy", 2.0 * (double)bytes);
-    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints);
+    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints, ls.events());
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
 }
 

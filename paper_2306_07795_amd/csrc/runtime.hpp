@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "bmmc.h"
+#include "kernels.hpp"
 #include "plan.hpp"
 
 namespace bmmc {
@@ -60,13 +61,18 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
 // Scratch of at least `bytes` for `stream` (caller holds ds->mu).
 int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out);
 
-// Record profiling events around a launch when profiling is on (caller holds ds->mu).
+// Timing of one launch when profiling is on (caller holds ds->mu): events()
+// go to a kernel launcher, which has the launch itself update them; for work
+// that is not one kernel launch (a graph), bracket() records them around it.
 struct LaunchScope {
     DeviceState* ds;
     hipStream_t stream;
-    ProfileEvent* ev = nullptr;
+    LaunchEv ev;  // null events when not profiling
+    bool bracketed = false;
     LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes);
     ~LaunchScope();
+    const LaunchEv& events() const { return ev; }
+    void bracket();
 };
 
 // Plan options from the public option struct.
@@ -99,7 +105,10 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
 uint64_t batch_signature(const bmmc_desc_t* descs, int count);
 
 // Tuning cache lookups (tune.cpp); false when nothing is cached.
-bool tuned_options(int n, int w, int method, bmmc_options_t* out);
+// Matrix class of the tuning cache: 1 for a matrix tiled at the default run
+// width (bit permutations among them), else 0.
+int matrix_class(const uint64_t* rows, int n);
+bool tuned_options(int n, int w, int method, int cls, bmmc_options_t* out);
 bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out);
 
 }  // namespace bmmc

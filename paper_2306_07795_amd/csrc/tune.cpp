@@ -1,5 +1,7 @@
 // Autotuner: times candidate tile shapes and launch parameters on the device
-// and caches the fastest, per (n, width, method) for single arrays and per
+// and caches the fastest, per (n, width, method, matrix class) for single
+// arrays -- class 0: matrices that are not tiled (general one-pass tiles or
+// two passes), class 1: tiled matrices such as bit permutations -- and per
 // batch signature for batched launches.  The cache can be saved to and loaded
 // from a JSON-lines file; BMMC_TUNE_CACHE names a file loaded on first use.
 #include <cinttypes>
@@ -19,7 +21,7 @@ namespace {
 struct TuneCache {
     std::mutex mu;
     bool loaded = false;
-    std::map<std::tuple<int, int, int>, std::pair<bmmc_options_t, double>> plain;
+    std::map<std::tuple<int, int, int, int>, std::pair<bmmc_options_t, double>> plain;
     std::map<uint64_t, std::pair<bmmc_batch_options_t, double>> batch;
 };
 
@@ -36,16 +38,17 @@ int load_file(TuneCache& c, const char* path) {
     while (std::fgets(line, sizeof(line), f)) {
         bmmc_options_t o;
         std::memset(&o, 0, sizeof(o));
-        int n, w, method;
+        int n, w, method, cls, used;
         double ms;
         if (std::sscanf(line,
-                        "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
-                        "\"iters\": %d, \"t\": %d, \"run_in\": %d, \"run_out\": %d, \"hints\": %d, "
-                        "\"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %lf}",
-                        &n, &w, &method, &o.threads, &o.iters, &o.t, &o.run_in, &o.run_out, &o.hints,
-                        &o.tile_order, &o.grid, &o.swizzle, &ms) == 13) {
-            o.method = method;
-            c.plain[{n, w, method}] = {o, ms};
+                        "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"class\": %d, "
+                        "\"used\": %d, \"threads\": %d, \"iters\": %d, \"t\": %d, \"run_in\": %d, "
+                        "\"run_out\": %d, \"hints\": %d, \"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, "
+                        "\"ms\": %lf}",
+                        &n, &w, &method, &cls, &used, &o.threads, &o.iters, &o.t, &o.run_in, &o.run_out,
+                        &o.hints, &o.tile_order, &o.grid, &o.swizzle, &ms) == 15) {
+            o.method = used;
+            c.plain[{n, w, method, cls}] = {o, ms};
             count++;
             continue;
         }
@@ -77,11 +80,13 @@ int save_file(TuneCache& c, const char* path) {
     for (auto& kv : c.plain) {
         const bmmc_options_t& o = kv.second.first;
         std::fprintf(f,
-                     "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"threads\": %d, "
-                     "\"iters\": %d, \"t\": %d, \"run_in\": %d, \"run_out\": %d, \"hints\": %d, "
-                     "\"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, \"ms\": %.6f}\n",
-                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), o.threads, o.iters,
-                     o.t, o.run_in, o.run_out, o.hints, o.tile_order, o.grid, o.swizzle, kv.second.second);
+                     "{\"kind\": \"plain\", \"n\": %d, \"w\": %d, \"method\": %d, \"class\": %d, "
+                     "\"used\": %d, \"threads\": %d, \"iters\": %d, \"t\": %d, \"run_in\": %d, "
+                     "\"run_out\": %d, \"hints\": %d, \"tile_order\": %d, \"grid\": %d, \"swizzle\": %d, "
+                     "\"ms\": %.6f}\n",
+                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                     o.method, o.threads, o.iters, o.t, o.run_in, o.run_out, o.hints, o.tile_order, o.grid,
+                     o.swizzle, kv.second.second);
     }
     for (auto& kv : c.batch) {
         const bmmc_batch_options_t& b = kv.second.first;
@@ -117,6 +122,20 @@ void random_matrix(int n, uint64_t seed, uint64_t* rows, uint64_t* c) {
     *c = next_rand(&seed) & low_mask(n);
 }
 
+// A random bit permutation with complement (tiled at every t) for timing.
+void random_bpc(int n, uint64_t seed, uint64_t* rows, uint64_t* c) {
+    int perm[64];
+    for (int i = 0; i < n; i++) perm[i] = i;
+    for (int i = n - 1; i > 0; i--) {
+        const int j = (int)(next_rand(&seed) % (uint64_t)(i + 1));
+        const int t = perm[i];
+        perm[i] = perm[j];
+        perm[j] = t;
+    }
+    for (int i = 0; i < n; i++) rows[i] = 1ull << perm[i];
+    *c = next_rand(&seed) & low_mask(n);
+}
+
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     Timer() {
@@ -131,11 +150,20 @@ struct Timer {
 
 }  // namespace
 
-bool tuned_options(int n, int w, int method, bmmc_options_t* out) {
+int matrix_class(const uint64_t* rows, int n) {
+    if (n <= 0 || !rows) return 0;
+    BitMat A;
+    A.n = n;
+    for (int i = 0; i < n; i++) A.r[i] = rows[i] & low_mask(n);
+    const int t = n < 6 ? n : 6;
+    return is_tiled(A, t) ? 1 : 0;
+}
+
+bool tuned_options(int n, int w, int method, int cls, bmmc_options_t* out) {
     TuneCache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
     ensure_loaded(c);
-    auto it = c.plain.find({n, w, method});
+    auto it = c.plain.find({n, w, method, cls});
     if (it == c.plain.end()) return false;
     *out = it->second.first;
     return true;
@@ -155,6 +183,13 @@ bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out) {
 
 using namespace bmmc;
 
+extern "C" int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows,
+                                bmmc_options_t* opts_out) {
+    if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
+    if (!opts_out || (n > 0 && !A_rows)) return set_error(BMMC_ERR_ARG, "NULL argument");
+    return tuned_options(n, elem_bytes, method, matrix_class(A_rows, n), opts_out) ? 1 : 0;
+}
+
 extern "C" int bmmc_tune_save(const char* path) {
     if (!path) return set_error(BMMC_ERR_ARG, "path is NULL");
     TuneCache& c = cache();
@@ -171,8 +206,73 @@ extern "C" int bmmc_tune_load(const char* path) {
     return load_file(c, path);
 }
 
+namespace bmmc {
+namespace {
+
+// Times the candidates on one matrix; the fastest options and time.
+void tune_matrix(DeviceState* ds, int n, int elem_bytes, int method, bool with_tiled, const uint64_t* rows,
+                 uint64_t c, const void* in, void* out, hipStream_t stream, int reps, bmmc_options_t* bo,
+                 double* best) {
+    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}};
+    *best = 1e30;
+    std::memset(bo, 0, sizeof(*bo));
+    Timer tm;
+    for (auto& sh : kShapes) {
+        if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
+        KernelShape ks = default_shape(elem_bytes);
+        ks.nt = sh[0];
+        ks.iters = sh[1];
+        const int D = ks.D();
+        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters, 0);
+        const int h = D / 2;
+        // (read-run, write-run) bits: square, and one bit longer on either side
+        const int runs[][2] = {{h, h}, {D - h, h}, {h, D - h}, {h + 1, D - h - 1}, {D - h - 1, h + 1}};
+        for (auto& ab : runs) {
+            if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
+            for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
+                for (int hints : {4, 2, 3}) {
+                    for (int order : {4, 2, 10}) {
+                        for (int g = 0; g < 2; g++) {
+                            bmmc_options_t o;
+                            std::memset(&o, 0, sizeof(o));
+                            // auto also tries the paper's two-pass scheme
+                            o.method = m == 0 ? method : BMMC_METHOD_TILED;
+                            o.t = ab[0] < ab[1] ? ab[0] : ab[1];
+                            o.run_in = ab[0];
+                            o.run_out = ab[1];
+                            o.threads = ks.nt;
+                            o.iters = ks.iters;
+                            o.swizzle = 1;
+                            o.hints = hints;
+                            o.tile_order = order;
+                            o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
+                            if (bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream) != BMMC_OK)
+                                continue;  // shape does not fit this size
+                            hipEventRecord(tm.a, stream);
+                            for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
+                            hipEventRecord(tm.b, stream);
+                            hipEventSynchronize(tm.b);
+                            float ms = 0;
+                            hipEventElapsedTime(&ms, tm.a, tm.b);
+                            const double per = ms / reps;
+                            if (per < *best) {
+                                *best = per;
+                                *bo = o;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+}  // namespace bmmc
+
 // Time tile shapes, run widths, cache hints, tile order and grid size on a
-// random permutation of 2^n elements; keep the fastest.
+// random permutation of 2^n elements (class 0) and on a random bit
+// permutation (class 1); keep the fastest of each.  Returns class 0's.
 extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, int reps,
                              bmmc_options_t* best_out, double* best_ms) {
     if (n < 1 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n out of range");
@@ -191,75 +291,32 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         return set_error(BMMC_ERR_NOMEM, "autotune buffers of %zu bytes", bytes);
     }
     hipMemsetAsync(in, 0x5a, bytes, stream);
-    uint64_t rows[64], c;
-    random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, rows, &c);
-
-    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}};
-    double best = 1e30;
-    bmmc_options_t bo;
-    std::memset(&bo, 0, sizeof(bo));
-    Timer tm;
-    for (auto& sh : kShapes) {
-        if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
-        KernelShape ks = default_shape(elem_bytes);
-        ks.nt = sh[0];
-        ks.iters = sh[1];
-        const int D = ks.D();
-        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters, 0);
-        const int h = D / 2;
-        // (read-run, write-run) bits: square, and one bit longer on either side
-        const int runs[][2] = {{h, h}, {D - h, h}, {h, D - h}, {h + 1, D - h - 1}, {D - h - 1, h + 1}};
-        for (auto& ab : runs) {
-            if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
-            for (int m = 0; m < (method == BMMC_METHOD_AUTO ? 2 : 1); m++) {
-                for (int hints : {4, 2, 3}) {
-                    for (int order : {4, 2, 10}) {
-                        for (int g = 0; g < 2; g++) {
-                            bmmc_options_t o;
-                            std::memset(&o, 0, sizeof(o));
-                            // auto also tries the paper's two-pass scheme
-                            o.method = m == 0 ? method : BMMC_METHOD_TILED;
-                            o.t = ab[0] < ab[1] ? ab[0] : ab[1];
-                            o.run_in = ab[0];
-                            o.run_out = ab[1];
-                            o.threads = ks.nt;
-                            o.iters = ks.iters;
-                            o.swizzle = 1;
-                            o.hints = hints;
-                            o.tile_order = order;
-                            o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
-                            st = bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                            if (st != BMMC_OK) continue;  // shape does not fit this size
-                            hipEventRecord(tm.a, stream);
-                            for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, rows, c, elem_bytes, &o, stream);
-                            hipEventRecord(tm.b, stream);
-                            hipEventSynchronize(tm.b);
-                            float ms = 0;
-                            hipEventElapsedTime(&ms, tm.a, tm.b);
-                            const double per = ms / reps;
-                            if (per < best) {
-                                best = per;
-                                bo = o;
-                            }
-                        }
-                    }
-                }
-            }
-        }
+    bmmc_options_t bo[2];
+    double best[2];
+    for (int cls = 0; cls < 2; cls++) {
+        uint64_t rows[64], c;
+        if (cls == 0)
+            random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, rows, &c);
+        else
+            random_bpc(n, 0x5A5A5A5Aull + (uint64_t)n, rows, &c);
+        // a tiled matrix is one tiled pass by every method but the general tile
+        tune_matrix(ds, n, elem_bytes, method, method == BMMC_METHOD_AUTO && cls == 0, rows, c, in, out, stream,
+                    reps, &bo[cls], &best[cls]);
     }
     hipStreamSynchronize(stream);
     hipFree(in);
     hipFree(out);
-    if (best >= 1e30) return set_error(BMMC_ERR_RANGE, "no tile shape fits n = %d, w = %d", n, elem_bytes);
+    if (best[0] >= 1e30 || best[1] >= 1e30)
+        return set_error(BMMC_ERR_RANGE, "no tile shape fits n = %d, w = %d", n, elem_bytes);
     {
         TuneCache& tc = cache();
         std::lock_guard<std::mutex> lk(tc.mu);
         ensure_loaded(tc);
-        tc.plain[{n, elem_bytes, method}] = {bo, best};
+        for (int cls = 0; cls < 2; cls++) tc.plain[{n, elem_bytes, method, cls}] = {bo[cls], best[cls]};
         autosave(tc);
     }
-    if (best_out) *best_out = bo;
-    if (best_ms) *best_ms = best;
+    if (best_out) *best_out = bo[0];
+    if (best_ms) *best_ms = best[0];
     return BMMC_OK;
 }
 

@@ -128,12 +128,13 @@ def test_batched_equals_separate_calls():
 def test_autotune_small_then_permute():
     opts, ms = B.bmmc_autotune(18, 4, B.METHOD_AUTO, G.stream(), 2)
     assert ms > 0 and opts["threads"] in (256, 512, 1024)
-    rows, c = gen.random_bmmc(18, 4)
     a = gen.data(18, 4, 4)
-    x, y = G.to_device(a), G.empty_like_bytes(a)
-    B.bmmc_permute(x, y, 18, rows, c, 4, G.stream())  # now uses the tuned shape
-    G.sync()
-    assert np.array_equal(G.to_host(y, a), O.permute(a, 18, rows, c))
+    for rows, c in (gen.random_bmmc(18, 4), (gen.bit_reversal_rows(18), 3)):
+        assert B.bmmc_tune_lookup(18, 4, rows) is not None  # each class tuned
+        x, y = G.to_device(a), G.empty_like_bytes(a)
+        B.bmmc_permute(x, y, 18, rows, c, 4, G.stream())  # now uses the tuned options
+        G.sync()
+        assert np.array_equal(G.to_host(y, a), O.permute(a, 18, rows, c))
 
 
 def test_autotune_batched_small():

@@ -356,3 +356,31 @@ def test_plain_layout_has_conflicts_that_the_swizzle_removes():
     swz = B.bmmc_emulate(a, out, n, rows, 0, 4)
     assert plain["lds_conflicts32"] > 0
     assert swz["lds_conflicts32"] == 0 and swz["lds_conflicts64"] == 0
+
+
+def test_tune_cache_classes_round_trip(tmp_path):
+    """Tuned options are kept per matrix class (tiled or not) and survive a
+    save / load; lookups pick the class of the matrix.  Sizes no other test
+    tunes, so the process-wide cache is not disturbed."""
+    n, w = 31, 2
+    rnd, _ = gen.random_bmmc(n, 3)
+    bpc, _ = gen.random_bpc(n, 4)
+    assert B.bmmc_tune_lookup(n, w, rnd) is None
+    path = tmp_path / "tune.jsonl"
+    lines = [
+        '{"kind": "plain", "n": 31, "w": 2, "method": 0, "class": 0, "used": 0, "threads": 512, "iters": 4, '
+        '"t": 6, "run_in": 7, "run_out": 6, "hints": 2, "tile_order": 4, "grid": 0, "swizzle": 1, "ms": 1.5}',
+        '{"kind": "plain", "n": 31, "w": 2, "method": 0, "class": 1, "used": 1, "threads": 256, "iters": 2, '
+        '"t": 6, "run_in": 6, "run_out": 6, "hints": 3, "tile_order": 2, "grid": 0, "swizzle": 1, "ms": 1.25}',
+    ]
+    path.write_text("\n".join(lines) + "\n")
+    assert B.bmmc_tune_load(str(path)) == 2
+    g = B.bmmc_tune_lookup(n, w, rnd)
+    assert (g["method"], g["threads"], g["run_in"], g["hints"]) == (0, 512, 7, 2)
+    t = B.bmmc_tune_lookup(n, w, bpc)
+    assert (t["method"], t["threads"], t["iters"], t["tile_order"]) == (1, 256, 2, 2)
+    assert B.bmmc_tune_lookup(n, w, rnd, B.METHOD_TILED) is None
+    out = tmp_path / "again.jsonl"
+    B.bmmc_tune_save(str(out))
+    saved = [l for l in out.read_text().splitlines() if '"n": 31, "w": 2' in l]
+    assert len(saved) == 2 and '"class": 1, "used": 1' in saved[1]
