@@ -233,10 +233,11 @@ typedef enum {
 
 /* How the network runs. */
 typedef enum {
-    /* parm compiled to BMMCs (Section 7.2) and fused (Section 3): each of the
-       n(n+1)/2 compare-exchange columns is one LDS-staged pass whose reads
-       and writes are coalesced, the compare-exchange done as the pass stores;
-       plus one final pass. */
+    /* parm compiled to BMMCs (Section 7.2) and fused (Section 3), then
+       consecutive stages grouped into LDS-staged passes whose reads and
+       writes are coalesced: each pass applies the product of its BMMCs and
+       runs its compare-exchange columns on every staged tile in LDS (a column
+       joins a pass when all its pairs lie inside the pass's tiles). */
     BMMC_SORTNET_PASSES = 0,
     /* every column in place at the keys' own positions (no permutations;
        accesses as scattered as the column's pairs): the uncompiled form */
@@ -252,6 +253,12 @@ typedef enum {
    _INTERNAL. */
 int bmmc_sortnet_stages(int n, uint64_t* rows_out, int max_matrices, int* count_out);
 
+/* The device passes of BMMC_SORTNET_PASSES for 2^n keys: *passes_out (the
+   number of passes, each one read and one write of the array) and
+   *columns_out (the most columns one pass runs); either may be NULL.
+   2 <= n <= BMMC_MAX_BITS.  Host only.  Errors: _RANGE, _INTERNAL. */
+int bmmc_sortnet_passes(int n, int* passes_out, int* columns_out);
+
 /* Sort 2^n 4-byte keys ascending with the sorting network of Section 7.1
    (even/odd merge sort, balanced periodic merger, written with parm):
    out = the keys of in in ascending key_type order.  in and out are distinct
@@ -259,6 +266,12 @@ int bmmc_sortnet_stages(int n, uint64_t* rows_out, int max_matrices, int* count_
    the library's per-stream scratch array of the same size.  Asynchronous on
    `stream`.  Errors: _ARG, _RANGE, _ALIAS, _NOMEM, _HIP, _INTERNAL. */
 int bmmc_sortnet(const void* in, void* out, int n, int key_type, int method, void* stream);
+
+/* Host emulation of bmmc_sortnet's BMMC_SORTNET_PASSES form, for tests: the
+   same passes with the same tables, tile by tile, on HOST memory (in/out are
+   host pointers); *passes_out (may be NULL) receives the number of passes.
+   2 <= n <= 24.  Errors: _ARG, _RANGE, _INTERNAL. */
+int bmmc_sortnet_emulate(const void* in, void* out, int n, int key_type, int* passes_out);
 
 /* Host emulation of the tiled kernels' address arithmetic, for tests: runs
    the same plan, tile by tile and lane by lane, on host memory (in/out are

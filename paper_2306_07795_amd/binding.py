@@ -109,6 +109,8 @@ def lib():
         "bmmc_permute_seq": (_i32, [_vp, _vp, _i32, _i32, P(_u64), P(_u64), _i32, _vp]),
         "bmmc_sortnet_stages": (_i32, [_i32, P(_u64), _i32, P(_i32)]),
         "bmmc_sortnet": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp]),
+        "bmmc_sortnet_emulate": (_i32, [_vp, _vp, _i32, _i32, P(_i32)]),
+        "bmmc_sortnet_passes": (_i32, [_i32, P(_i32), P(_i32)]),
         "bmmc_plan_ex": (_i32, [P(_u64), _u64, _i32, _i32, P(Options), P(Plan)]),
         "bmmc_factorize_ulp": (_i32, [P(_u64), _i32, P(_u64), P(_u64), P(_u64), P(_u64), P(_u64)]),
         "bmmc_permute": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp]),
@@ -156,7 +158,7 @@ def exported_names():
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
-        "bmmc_tune_lookup",
+        "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes",
     ]
 
 
@@ -294,6 +296,21 @@ def bmmc_sortnet_stages(n: int):
     rows = (_u64 * max(count.value * n, 1))()
     _check(lib().bmmc_sortnet_stages(n, rows, count.value, _c.byref(count)))
     return [[int(rows[s * n + i]) for i in range(n)] for s in range(count.value)]
+
+
+def bmmc_sortnet_passes(n: int):
+    """(passes, most columns in one pass) of the compiled network."""
+    p, c = _c.c_int(0), _c.c_int(0)
+    _check(lib().bmmc_sortnet_passes(n, _c.byref(p), _c.byref(c)))
+    return p.value, c.value
+
+
+def bmmc_sortnet_emulate(inp, out, n: int, key_type: int = KEY_I32) -> int:
+    """Host emulation of the network's passes on numpy arrays; returns the
+    number of passes."""
+    count = _c.c_int(0)
+    _check(lib().bmmc_sortnet_emulate(_ptr(inp), _ptr(out), n, key_type, _c.byref(count)))
+    return count.value
 
 
 def bmmc_sortnet(inp, out, n: int, key_type: int = KEY_I32, method: int = SORTNET_PASSES, stream=None):

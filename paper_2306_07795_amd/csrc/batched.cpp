@@ -27,9 +27,10 @@ struct BatchState {
     void* host = nullptr;  // pinned staging of the same layout
     size_t cap_passes = 0, cap_items = 0;
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
-    hipGraphExec_t exec = nullptr;
-    uint32_t exec_grid = 0;
-    int exec_hints = -1;
+    // one captured graph per cache-hint setting (batches of different sizes
+    // alternate between them), each for one grid size
+    hipGraphExec_t exec[4] = {};
+    uint32_t exec_grid[4] = {};
 };
 
 struct BatchRegistry {
@@ -71,9 +72,9 @@ int ensure_capacity(BatchState* bs, size_t np, size_t ni) {
         hipHostFree(bs->host);
         bs->dev = bs->host = nullptr;
     }
-    if (bs->exec) {
-        hipGraphExecDestroy(bs->exec);
-        bs->exec = nullptr;
+    for (hipGraphExec_t& g : bs->exec) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
     }
     e = hipMalloc(&bs->dev, L.total);
     if (e != hipSuccess) {
@@ -142,15 +143,15 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipG
 }
 
 int build_graph(BatchState* bs, uint32_t grid, int hints) {
-    if (bs->exec && bs->exec_grid == grid && bs->exec_hints == hints) return BMMC_OK;
-    if (bs->exec) {
-        hipGraphExecDestroy(bs->exec);
-        bs->exec = nullptr;
+    hipGraphExec_t& g = bs->exec[hints & 3];
+    if (g && bs->exec_grid[hints & 3] == grid) return BMMC_OK;
+    if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
     }
-    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, &bs->exec);
+    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, &g);
     if (st != BMMC_OK) return st;
-    bs->exec_grid = grid;
-    bs->exec_hints = hints;
+    bs->exec_grid[hints & 3] = grid;
     return BMMC_OK;
 }
 
@@ -348,9 +349,8 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
         if (st != BMMC_OK) return st;
     }
     LaunchScope ls(ds, stream, "k_batched", moved);
-    ls.bracket();
     if (o.use_graph >= 0) {
-        e = hipGraphLaunch(bs->exec, stream);
+        e = hipGraphLaunch(bs->exec[hints & 3], stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
         e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, stream);
@@ -526,7 +526,6 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     for (auto& ba : pb->arrays) any |= !ba.single;
     if (!any) return BMMC_OK;
     LaunchScope ls(ds, stream, "k_batched", pb->moved);
-    ls.bracket();
     hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
                                  : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, stream);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "batch launch");

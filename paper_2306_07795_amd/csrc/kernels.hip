@@ -5,7 +5,6 @@
 // output addresses are a per-tile scalar part XOR a per-thread part computed
 // once XOR a compile-time-selected per-iteration part, so the per-element cost
 // is one XOR and one shift whatever the matrix.
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -55,21 +54,6 @@ __device__ __forceinline__ uint32_t lin_const(const uint32_t* tab, uint32_t v) {
     for (int k = 0; k < NBITS; k++)
         if ((v >> k) & 1u) r ^= tab[BASE + k];
     return r;
-}
-
-// Compare-exchange of the element pairs (0, 1) and (2, 3) of a vector of four
-// 4-byte keys, the smaller key first: OP 1 orders them as int32, OP 2 as
-// uint32 (one column of the sorting network of Section 7.1, in the index space
-// where its pairs are adjacent).
-template <int OP>
-__device__ __forceinline__ void cmpx_pairs(Vec16<4>& o) {
-#pragma unroll
-    for (int p = 0; p < 4; p += 2) {
-        const uint32_t a = o.e[p], b = o.e[p + 1];
-        const bool swap = OP == 1 ? (int32_t)a > (int32_t)b : a > b;
-        o.e[p] = swap ? b : a;
-        o.e[p + 1] = swap ? a : b;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -153,12 +137,9 @@ struct TileCtx {
     }
 
     // Write phase: gather each output vector from slots G(u), store it to
-    // one output run at T.r XOR c XOR Y(u).  OP != 0 compare-exchanges the
-    // key pairs of each vector on the way (4-byte keys only).
-    template <int OP = 0>
+    // one output run at T.r XOR c XOR Y(u).
     __device__ __forceinline__ void store(const PassTables& P, g_u32x4* __restrict__ out, const E* lds,
                                           const Parts& pt, uint32_t tid) const {
-        static_assert(OP == 0 || W == 4, "compare-exchange needs 4-byte keys");
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
@@ -166,7 +147,6 @@ struct TileCtx {
                 Vec16<W> o;
 #pragma unroll
                 for (int e = 0; e < VEC; e++) o.e[e] = lds[g ^ lin_const<0, LV>(P.G, e)];
-                if constexpr (OP != 0) cmpx_pairs<OP>(o);
                 const uint32_t y = pt.yb ^ yt ^ lin_const<LV + LT, LI>(P.Y, it);
                 st16<HINT>(out + (y >> LV), o.v);
             }
@@ -176,10 +156,16 @@ struct TileCtx {
     // Tiles first, first + step, ... below last.  The loads of the next tile
     // are issued right after the barrier that ends the current tile's LDS
     // writes, so they are in flight while the current tile is written out.
-    template <int OP = 0>
+    // mid(parts) runs on the staged tile before it is written out (its own
+    // barriers included).
+    struct NoMid {
+        __device__ __forceinline__ void operator()(const Parts&) const {}
+    };
+    template <typename Mid = NoMid>
     __device__ __forceinline__ void run_tiles(const PassTables& P, const g_u32x4* __restrict__ in,
                                               g_u32x4* __restrict__ out, E* lds, uint32_t first,
-                                              uint32_t last, uint32_t step, uint32_t tid) const {
+                                              uint32_t last, uint32_t step, uint32_t tid,
+                                              const Mid& mid = Mid()) const {
         if (first >= last) return;
         Vec16<W> buf[ITERS];
         uint32_t tile = first;
@@ -195,7 +181,8 @@ struct TileCtx {
                 nxt = parts(P, next);
                 load(P, in, nxt.r, tid, buf);
             }
-            store<OP>(P, out, lds, cur, tid);
+            mid(cur);
+            store(P, out, lds, cur, tid);
             __syncthreads();
             if (!more) break;
             tile = next;
@@ -262,51 +249,87 @@ bool tiled_kernel_available(int w, int nt, int iters, int hints) {
 
 hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, void* out,
                         const PassTables& tab, uint32_t ntiles, uint32_t grid, uint32_t xcds,
-                        hipStream_t stream, const LaunchEv& ev) {
+                        hipStream_t stream) {
     const TiledEntry* e = find_tiled(w, nt, iters, hints);
     if (!e) return hipErrorInvalidValue;
     if (grid == 0 || grid > ntiles) grid = ntiles;
-    hipExtLaunchKernelGGL(e->fn, dim3(grid), dim3(nt), 0, stream, ev.start, ev.stop, 0, (const u32x4*)in,
-                          (u32x4*)out, tab, ntiles, xcds);
+    hipLaunchKernelGGL(e->fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab, ntiles, xcds);
     return hipGetLastError();
 }
 
-// A tiled pass of 4-byte keys whose store compare-exchanges adjacent pairs.
+// ---------------------------------------------------------------------------
+// Several columns of the sorting network per pass: between the read and the
+// write phase each column compare-exchanges, in LDS, the pairs of slots
+// (s, s XOR f) of the staged tile; a barrier separates the columns.  Pair k
+// of a column is the slot s0 that has bit p = lowest set bit of f cleared,
+// the other bits those of k, and its partner s0 XOR f.
+// ---------------------------------------------------------------------------
+template <int OP>
+struct NetMid {
+    const NetColumns& C;
+    uint32_t* lds;
+    uint32_t npairs;  // 2^(d-1)
+    uint32_t tid, nt;
+    template <typename PartsT>
+    __device__ __forceinline__ void operator()(const PartsT& pt) const {
+        for (uint32_t i = 0; i < C.count; i++) {
+            const NetCol c = C.col[i];
+            const uint32_t p = __builtin_ctz(c.f);
+            const uint32_t lo = (1u << p) - 1u;
+            const uint32_t alpha = __builtin_popcount(c.g & pt.r) & 1u;
+            for (uint32_t k = tid; k < npairs; k += nt) {
+                const uint32_t s0 = ((k & ~lo) << 1) | (k & lo);
+                const uint32_t s1 = s0 ^ c.f;
+                const uint32_t a = lds[s0], b = lds[s1];
+                // bit 0 of s0's index in the column's space: 0 keeps the smaller
+                const uint32_t hi0 = alpha ^ (__builtin_popcount(c.beta & s0) & 1u);
+                const bool gt = OP == 1 ? (int32_t)a > (int32_t)b : a > b;
+                if (gt != (hi0 != 0)) {
+                    lds[s0] = b;
+                    lds[s1] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
 template <int NT, int ITERS, int OP>
 __global__ void __launch_bounds__(NT)
-k_tiled_cmp(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, uint32_t ntiles,
-            uint32_t xcds) {
-    using C = TileCtx<4, NT, ITERS, 0>;
-    __shared__ typename C::E lds[1 << C::D];
-    C ctx;
+k_tiled_net(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, const NetColumns C,
+            uint32_t ntiles, uint32_t xcds) {
+    using Ctx = TileCtx<4, NT, ITERS, 0>;
+    __shared__ typename Ctx::E lds[1 << Ctx::D];
+    Ctx ctx;
     ctx.init(P, threadIdx.x);
-    ctx.template run_tiles<OP>(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles,
-                               gridDim.x, threadIdx.x);
+    const NetMid<OP> mid{C, lds, 1u << (P.d - 1), threadIdx.x, NT};
+    ctx.run_tiles(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles, gridDim.x, threadIdx.x,
+                  mid);
 }
 
-struct TiledCmpEntry {
+struct TiledNetEntry {
     int nt, iters, op;
-    void (*fn)(const u32x4*, u32x4*, const PassTables, uint32_t, uint32_t);
+    void (*fn)(const u32x4*, u32x4*, const PassTables, const NetColumns, uint32_t, uint32_t);
 };
-static const TiledCmpEntry kTiledCmp[] = {
-    {256, 4, 1, k_tiled_cmp<256, 4, 1>}, {256, 4, 2, k_tiled_cmp<256, 4, 2>},
-    {256, 8, 1, k_tiled_cmp<256, 8, 1>}, {256, 8, 2, k_tiled_cmp<256, 8, 2>},
+static const TiledNetEntry kTiledNet[] = {
+    {256, 8, 1, k_tiled_net<256, 8, 1>}, {256, 8, 2, k_tiled_net<256, 8, 2>},
+    {256, 4, 1, k_tiled_net<256, 4, 1>}, {256, 4, 2, k_tiled_net<256, 4, 2>},
 };
 
-bool tiled_cmp_available(int nt, int iters) {
-    for (const auto& e : kTiledCmp)
+bool tiled_net_available(int nt, int iters) {
+    for (const auto& e : kTiledNet)
         if (e.nt == nt && e.iters == iters) return true;
     return false;
 }
 
-hipError_t launch_tiled_cmp(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
-                            uint32_t ntiles, uint32_t grid, uint32_t xcds, hipStream_t stream,
-                            const LaunchEv& ev) {
-    for (const auto& e : kTiledCmp) {
+hipError_t launch_tiled_net(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
+                            const NetColumns& cols, uint32_t ntiles, uint32_t grid, hipStream_t stream) {
+    if (tab.d < 1) return hipErrorInvalidValue;
+    for (const auto& e : kTiledNet) {
         if (e.nt != nt || e.iters != iters || e.op != op) continue;
         if (grid == 0 || grid > ntiles) grid = ntiles;
-        hipExtLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, ev.start, ev.stop, 0, (const u32x4*)in,
-                              (u32x4*)out, tab, ntiles, xcds);
+        hipLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab, cols, ntiles,
+                           0u);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -340,16 +363,14 @@ k_cmp_direct(uint32_t* __restrict__ data, const DirectArgs P) {
     data[p1] = swap ? a : c;
 }
 
-hipError_t launch_cmp_direct(void* data, const DirectArgs& args, int op, hipStream_t stream, const LaunchEv& ev) {
+hipError_t launch_cmp_direct(void* data, const DirectArgs& args, int op, hipStream_t stream) {
     if (args.n < 1 || args.n > kMaxTbBits) return hipErrorInvalidValue;
     const uint64_t pairs = 1ull << (args.n - 1);
     const uint32_t grid = (uint32_t)((pairs + 255) / 256);
     if (op == 1)
-        hipExtLaunchKernelGGL(k_cmp_direct<1>, dim3(grid), dim3(256), 0, stream, ev.start, ev.stop, 0,
-                              (uint32_t*)data, args);
+        hipLaunchKernelGGL(k_cmp_direct<1>, dim3(grid), dim3(256), 0, stream, (uint32_t*)data, args);
     else if (op == 2)
-        hipExtLaunchKernelGGL(k_cmp_direct<2>, dim3(grid), dim3(256), 0, stream, ev.start, ev.stop, 0,
-                              (uint32_t*)data, args);
+        hipLaunchKernelGGL(k_cmp_direct<2>, dim3(grid), dim3(256), 0, stream, (uint32_t*)data, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -390,7 +411,7 @@ k_naive(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, const NaiveAr
 }
 
 hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs& args,
-                        hipStream_t stream, const LaunchEv& ev) {
+                        hipStream_t stream) {
     const uint64_t size = 1ull << n;
     const int vec = 16 / w;
     const bool vector = size >= (uint64_t)vec * 256;
@@ -401,11 +422,9 @@ hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs
 #define BMMC_NAIVE(WW)                                                                            \
     case WW:                                                                                      \
         if (vector)                                                                               \
-            hipExtLaunchKernelGGL((k_naive<WW, 16 / WW>), dim3(grid), dim3(256), 0, stream, ev.start, \
-                                  ev.stop, 0, i8, o8, args);                                       \
+            hipLaunchKernelGGL((k_naive<WW, 16 / WW>), dim3(grid), dim3(256), 0, stream, i8, o8, args); \
         else                                                                                      \
-            hipExtLaunchKernelGGL((k_naive<WW, 1>), dim3(grid), dim3(256), 0, stream, ev.start,     \
-                                  ev.stop, 0, i8, o8, args);                                       \
+            hipLaunchKernelGGL((k_naive<WW, 1>), dim3(grid), dim3(256), 0, stream, i8, o8, args);       \
         break;
     switch (w) {
         BMMC_NAIVE(1)
@@ -441,19 +460,16 @@ __global__ void k_copy_tail(const uint8_t* in, uint8_t* out, uint32_t count) {
     if (i < count) out[i] = in[i];
 }
 
-hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt, int hints,
-                       const LaunchEv& ev) {
+hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt, int hints) {
     const uint64_t nvec = bytes / 16;
     const uint32_t tail = (uint32_t)(bytes % 16);
-    // the start event goes with the first kernel, the stop event with the last
-    const hipEvent_t e0 = ev.start, e1 = tail ? nullptr : ev.stop;
     if (nvec) {
         const uint64_t per = 256ull * (uint64_t)vpt;
         const dim3 grid((uint32_t)((nvec + per - 1) / per));
         const u32x4* i4 = (const u32x4*)in;
         u32x4* o4 = (u32x4*)out;
 #define BMMC_COPY_H(V, H) \
-    hipExtLaunchKernelGGL((k_copy<V, H>), grid, dim3(256), 0, stream, e0, e1, 0, i4, o4, nvec)
+    hipLaunchKernelGGL((k_copy<V, H>), grid, dim3(256), 0, stream, i4, o4, nvec)
 #define BMMC_COPY(V)                            \
     case V:                                     \
         switch (hints) {                        \
@@ -474,8 +490,8 @@ hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stre
 #undef BMMC_COPY_H
     }
     if (tail)
-        hipExtLaunchKernelGGL(k_copy_tail, dim3(1), dim3(16), 0, stream, nvec ? nullptr : ev.start, ev.stop, 0,
-                              (const uint8_t*)in + nvec * 16, (uint8_t*)out + nvec * 16, tail);
+        hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(16), 0, stream, (const uint8_t*)in + nvec * 16,
+                           (uint8_t*)out + nvec * 16, tail);
     return hipGetLastError();
 }
 

@@ -8,14 +8,6 @@
 
 namespace bmmc {
 
-// Optional per-launch timing: events that the launch itself updates with the
-// kernel's start and stop times (hipExtLaunchKernel), so timing adds no
-// commands to the stream.  Null events: a plain launch.
-struct LaunchEv {
-    hipEvent_t start = nullptr;
-    hipEvent_t stop = nullptr;
-};
-
 // Column masks of A for the naive kernel: col[j] = A.e_j (0 for j >= n).
 struct NaiveArgs {
     uint32_t n;
@@ -33,15 +25,14 @@ bool tiled_kernel_available(int w, int nt, int iters, int hints = 0);
 // round-robin) a contiguous range of tiles.
 hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, void* out,
                         const PassTables& tab, uint32_t ntiles, uint32_t grid, uint32_t xcds,
-                        hipStream_t stream, const LaunchEv& ev = LaunchEv());
+                        hipStream_t stream);
 
-// Tiled pass of 4-byte keys that compare-exchanges the pairs (2k, 2k + 1) of
-// its output as it stores them (op 1: int32 order, 2: uint32 order).  Shapes
-// (nt, iters) = (256, 4) and (256, 8).
-bool tiled_cmp_available(int nt, int iters);
-hipError_t launch_tiled_cmp(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
-                            uint32_t ntiles, uint32_t grid, uint32_t xcds, hipStream_t stream,
-                            const LaunchEv& ev = LaunchEv());
+// Tiled pass of 4-byte keys that runs the sorting-network columns `cols` on
+// each staged tile in LDS before writing it (op 1: int32 order, 2: uint32).
+// Shapes (nt, iters) = (256, 8) and (256, 4).
+bool tiled_net_available(int nt, int iters);
+hipError_t launch_tiled_net(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
+                            const NetColumns& cols, uint32_t ntiles, uint32_t grid, hipStream_t stream);
 
 // One sorting-network column in place at the keys' own positions: the pair k
 // sits at Q.(2k) and Q.(2k) XOR Q.e_0, col[j] = Q.e_j (0 for j >= n), n >= 1.
@@ -49,18 +40,17 @@ struct DirectArgs {
     uint32_t n;
     uint32_t col[kMaxTbBits];
 };
-hipError_t launch_cmp_direct(void* data, const DirectArgs& args, int op, hipStream_t stream,
-                             const LaunchEv& ev = LaunchEv());
+hipError_t launch_cmp_direct(void* data, const DirectArgs& args, int op, hipStream_t stream);
 
 // Naive kernel: 2^n elements, one 16-byte vector (or one element when
 // 2^n * w < 16 * 256) per lane, scattered element stores.
 hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs& args,
-                        hipStream_t stream, const LaunchEv& ev = LaunchEv());
+                        hipStream_t stream);
 
 // 16-byte vector copy of `bytes` bytes (tail handled bytewise), vpt vectors
 // per lane (1, 2, 4, 8).
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stream, int vpt = 4,
-                       int hints = 0, const LaunchEv& ev = LaunchEv());
+                       int hints = 0);
 
 // Batched persistent kernel: runs items range[phase] .. range[phase + 1]
 // (device pointers; *head must be zero at launch).

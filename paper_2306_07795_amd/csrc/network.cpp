@@ -9,11 +9,17 @@
 // 2^(n-1), which keeps the low index bits), smaller key first.  Adjacent BMMCs
 // fuse by composition (Section 3), so the network is
 //     M_0, C, M_1, C, ..., C, M_S      (S = n(n+1)/2 columns)
-// and M_S ... M_0 = I.  On the device each M_s with its column is one tiled
-// pass whose store compare-exchanges the pairs of every 16-byte vector; M_S is
-// a plain pass.  The direct form runs the columns in place at the keys' own
-// positions (pair k of column s at P_s^-1.(2k), P_s^-1.(2k + 1) with
-// P_s = M_s ... M_0), without the permutations.
+// and M_S ... M_0 = I.  On the device consecutive stages are grouped into
+// tiled passes: a pass applies T = M_e ... M_s and runs the columns C_s .. C_e
+// on each staged tile in LDS, which works as long as every column's pairs lie
+// inside the tile -- the pass's tile subspace then contains the pair vectors
+// P^-1.e_0 of all its columns (P the product of the pass's matrices up to the
+// column) besides the low input bits and T^-1 of the low output bits that
+// keep the reads and writes coalesced.  Stages are added to a pass greedily
+// while that subspace fits the tile.  The direct form runs the columns in
+// place at the keys' own positions (pair k of column s at Q.(2k),
+// Q.(2k + 1) with Q = (M_s ... M_0)^-1), without the permutations.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -114,7 +120,7 @@ int run_direct(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
     std::lock_guard<std::mutex> lk(ds->mu);
     {
         LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
-        hipError_t e = launch_copy(in, out, bytes, stream, 4, 0, ls.events());
+        hipError_t e = launch_copy(in, out, bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "copy launch");
     }
     BitMat P = BitMat::identity(n);
@@ -127,59 +133,261 @@ int run_direct(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
         da.n = (uint32_t)n;
         for (int j = 0; j < n; j++) da.col[j] = (uint32_t)Q.col(j);
         LaunchScope ls(ds, stream, op == 1 ? "k_cmp_direct<1>" : "k_cmp_direct<2>", 2.0 * bytes);
-        hipError_t e = launch_cmp_direct(out, da, op, stream, ls.events());
+        hipError_t e = launch_cmp_direct(out, da, op, stream);
         if (e != hipSuccess) return hip_fail(e, "direct column launch");
     }
+    return BMMC_OK;
+}
+
+// Tile shape and run bits of the network's passes: 2^13-key tiles with
+// reads and writes in runs of 2^6 keys (256 bytes), so that every pass holds
+// at least one column (6 + 6 + 1 <= 13).
+constexpr int kNetThreads = 256, kNetIters = 8, kNetRunIn = 6, kNetRunOut = 6;
+
+struct NetPass {
+    PassPlan plan;
+    NetColumns cols;
+};
+
+KernelShape net_shape() {
+    KernelShape ks = default_shape(4);
+    ks.nt = kNetThreads;
+    ks.iters = kNetIters;
+    return ks;
+}
+
+// Does the tile subspace of a pass T holding the pair vectors `us` fit?
+bool fits(const BitMat& T, const std::vector<uint64_t>& us, int D) {
+    const int n = T.n;
+    if (n <= D) return (int)us.size() <= kMaxNetCols;
+    if ((int)us.size() > kMaxNetCols) return false;
+    BitMat Ti;
+    if (!inverse(T, &Ti)) return false;
+    Basis b;
+    for (int k = 0; k < kNetRunIn && k < n; k++) b.insert(1ull << k);
+    for (int k = 0; k < kNetRunOut && k < n; k++) b.insert(Ti.col(k));
+    for (uint64_t u : us) b.insert(u);
+    return b.count <= D;
+}
+
+// Column i of a pass, in the slot space of its tile: f = F(coordinates of the
+// pair vector u), beta = the direction functional g read through X and F^-1.
+int column_tables(const PassTables& tab, uint64_t u, uint64_t g, NetCol* out) {
+    Basis xb;
+    for (uint32_t k = 0; k < tab.d; k++) xb.insert(tab.X[k]);
+    const uint64_t cu = xb.coords(u);
+    if (cu == ~0ull) return BMMC_ERR_INTERNAL;
+    uint32_t f = 0;
+    for (uint64_t m = cu; m; m &= m - 1) f ^= tab.F[__builtin_ctzll(m)];
+    uint32_t beta = 0;
+    for (uint32_t k = 0; k < tab.d; k++) {
+        // coordinates v with F(v) = e_k (F has its top bit of column j at j)
+        uint32_t t = 1u << k, v = 0;
+        for (int j = (int)tab.d - 1; j >= 0; j--)
+            if ((t >> j) & 1u) {
+                v |= 1u << j;
+                t ^= tab.F[j];
+            }
+        uint32_t x = 0;
+        for (uint32_t m = v; m; m &= m - 1) x ^= tab.X[__builtin_ctz(m)];
+        beta |= (uint32_t)(__builtin_popcountll(g & x) & 1) << k;
+    }
+    // the two slots of a pair sit on opposite sides of the column
+    if (f == 0 || (__builtin_popcount(beta & f) & 1) != 1) return BMMC_ERR_INTERNAL;
+    out->f = f;
+    out->beta = beta;
+    out->g = (uint32_t)g;
+    return BMMC_OK;
+}
+
+int build_net_pass(const BitMat& T, const std::vector<uint64_t>& us, const std::vector<uint64_t>& gs,
+                   uint64_t seed, NetPass* np) {
+    const KernelShape ks = net_shape();
+    int st = build_pass(T, 0, kNetRunIn, kNetRunOut, ks, 1, seed, &np->plan, 0, 0, us.data(), (int)us.size());
+    if (st != BMMC_OK) return st;
+    std::memset(&np->cols, 0, sizeof(np->cols));
+    np->cols.count = (uint32_t)us.size();
+    for (size_t i = 0; i < us.size(); i++) {
+        st = column_tables(np->plan.tab, us[i], gs[i], &np->cols.col[i]);
+        if (st != BMMC_OK) return st;
+    }
+    return BMMC_OK;
+}
+
+// Greedy grouping of M_0, C_0, ..., C_(S-1), M_S into passes.
+int group_passes(const std::vector<BitMat>& st, int n, std::vector<NetPass>* out) {
+    const int D = net_shape().D();
+    const size_t S = st.size() - 1;
+    size_t s = 0;
+    uint64_t seed = 0x6E65747Full ^ (uint64_t)n;
+    while (s < S) {
+        BitMat T = st[s];
+        BitMat Ti;
+        inverse(T, &Ti);
+        std::vector<uint64_t> us{Ti.col(0)}, gs{T.r[0]};
+        size_t e = s;
+        while (e + 1 < S) {  // the next matrix with its column
+            const BitMat T2 = mul(st[e + 1], T);
+            BitMat T2i;
+            inverse(T2, &T2i);
+            us.push_back(T2i.col(0));
+            if (!fits(T2, us, D)) {
+                us.pop_back();
+                break;
+            }
+            gs.push_back(T2.r[0]);
+            T = T2;
+            e++;
+        }
+        if (e + 1 == S) {  // the final matrix, if it fits too
+            const BitMat T2 = mul(st[S], T);
+            if (fits(T2, us, D)) {
+                T = T2;
+                e = S;
+            }
+        }
+        NetPass np;
+        int rc = build_net_pass(T, us, gs, seed++, &np);
+        if (rc != BMMC_OK) return rc;
+        out->push_back(np);
+        s = e + 1;
+    }
+    if (s == S) {  // the final matrix alone
+        NetPass np;
+        int rc = build_net_pass(st[S], {}, {}, seed++, &np);
+        if (rc != BMMC_OK) return rc;
+        out->push_back(np);
+    }
+    return BMMC_OK;
+}
+
+std::mutex g_pass_mu;
+std::map<int, std::vector<NetPass>> g_passes;
+
+int passes_for(int n, const std::vector<BitMat>& st, const std::vector<NetPass>** out) {
+    std::lock_guard<std::mutex> lk(g_pass_mu);
+    auto it = g_passes.find(n);
+    if (it == g_passes.end()) {
+        std::vector<NetPass> v;
+        int rc = group_passes(st, n, &v);
+        if (rc != BMMC_OK) return set_error(rc, "grouping the network of n = %d into passes failed", n);
+        it = g_passes.emplace(n, std::move(v)).first;
+    }
+    *out = &it->second;
     return BMMC_OK;
 }
 
 int run_passes(DeviceState* ds, const std::vector<BitMat>& st, const void* in, void* out, int n, int op,
                hipStream_t stream) {
     const size_t bytes = (size_t)4 << n;
-    // one plan per stage (cached by matrix), before taking the device lock
-    std::vector<std::shared_ptr<const Plan>> plans(st.size());
-    PlanOptions po;
-    po.method = kMethodAuto;
-    for (size_t s = 0; s < st.size(); s++) {
-        int rc = get_plan(ds, st[s].r, 0, n, 4, po, &plans[s]);
-        if (rc != BMMC_OK) return rc;
-        const Plan& p = *plans[s];
-        if (p.naive || p.npass != 1) return set_error(BMMC_ERR_INTERNAL, "network stage %zu is not one pass", s);
-        if (s + 1 < st.size() && !tiled_cmp_available(p.shape.nt, p.shape.iters))
-            return set_error(BMMC_ERR_INTERNAL, "no compare-exchange pass for threads=%d iters=%d", p.shape.nt,
-                             p.shape.iters);
-    }
+    const std::vector<NetPass>* passes = nullptr;
+    int rc = passes_for(n, st, &passes);
+    if (rc != BMMC_OK) return rc;
     std::lock_guard<std::mutex> lk(ds->mu);
     void* mid = nullptr;
-    int rc = get_scratch(ds, stream, bytes, &mid);
-    if (rc != BMMC_OK) return rc;
+    if (passes->size() > 1) {
+        rc = get_scratch(ds, stream, bytes, &mid);
+        if (rc != BMMC_OK) return rc;
+    }
     // the last pass writes `out`; the ones before alternate with scratch
-    const size_t last = st.size() - 1;
+    const size_t last = passes->size() - 1;
     const void* src = in;
     char name[64];
-    for (size_t s = 0; s <= last; s++) {
-        void* dst = ((last - s) % 2 == 0) ? out : mid;
-        const Plan& p = *plans[s];
-        if (s == last) {
-            rc = enqueue_plan(ds, p, src, dst, stream, 0);
-            if (rc != BMMC_OK) return rc;
-        } else {
-            const PassTables& tab = p.pass[0].tab;
-            snprintf(name, sizeof(name), "k_tiled_cmp<%d,%d,%d>", p.shape.nt, p.shape.iters, op);
-            LaunchScope ls(ds, stream, name, 2.0 * bytes);
-            hipError_t e = launch_tiled_cmp(p.shape.nt, p.shape.iters, op, src, dst, tab, 1u << tab.ntb, 0, 0,
-                                            stream, ls.events());
-            if (e != hipSuccess) return hip_fail(e, "compare-exchange pass launch");
-        }
+    for (size_t k = 0; k <= last; k++) {
+        void* dst = ((last - k) % 2 == 0) ? out : mid;
+        const NetPass& np = (*passes)[k];
+        const PassTables& tab = np.plan.tab;
+        snprintf(name, sizeof(name), "k_tiled_net<%d,%d,%d>", kNetThreads, kNetIters, op);
+        LaunchScope ls(ds, stream, name, 2.0 * bytes);
+        hipError_t e =
+            launch_tiled_net(kNetThreads, kNetIters, op, src, dst, tab, np.cols, 1u << tab.ntb, 0, stream);
+        if (e != hipSuccess) return hip_fail(e, "sorting-network pass launch");
         src = dst;
     }
     return BMMC_OK;
+}
+
+// Host emulation of one k_tiled_net pass with the same tables: tile by tile,
+// the read phase by X and F, the columns by f, beta and g, the write phase by
+// Y and G.
+void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* dst) {
+    const PassTables& P = np.plan.tab;
+    const uint32_t d = P.d, slots = 1u << d;
+    std::vector<uint32_t> lds(slots);
+    auto lin = [](const uint32_t* tab, uint32_t v) {
+        uint32_t r = 0;
+        for (; v; v &= v - 1) r ^= tab[__builtin_ctz(v)];
+        return r;
+    };
+    for (uint32_t tile = 0; tile < (1u << P.ntb); tile++) {
+        uint32_t r = 0, yb = P.c_hi, gx = P.c_lds;
+        for (uint32_t j = 0; j < P.ntb; j++)
+            if ((tile >> j) & 1u) {
+                r ^= P.tb[j][0];
+                yb ^= P.tb[j][1];
+                gx ^= P.tb[j][2];
+            }
+        for (uint32_t v = 0; v < slots; v++) lds[lin(P.F, v)] = src[r ^ lin(P.X, v)];
+        for (uint32_t i = 0; i < np.cols.count; i++) {
+            const NetCol& c = np.cols.col[i];
+            const uint32_t p = __builtin_ctz(c.f), lo = (1u << p) - 1u;
+            const uint32_t alpha = __builtin_popcount(c.g & r) & 1u;
+            for (uint32_t k = 0; k < slots / 2; k++) {
+                const uint32_t s0 = ((k & ~lo) << 1) | (k & lo), s1 = s0 ^ c.f;
+                const uint32_t a = lds[s0], b = lds[s1];
+                const uint32_t hi0 = alpha ^ (__builtin_popcount(c.beta & s0) & 1u);
+                const bool gt = op == 1 ? (int32_t)a > (int32_t)b : a > b;
+                if (gt != (hi0 != 0)) {
+                    lds[s0] = b;
+                    lds[s1] = a;
+                }
+            }
+        }
+        for (uint32_t u = 0; u < slots; u++) dst[yb ^ lin(P.Y, u)] = lds[gx ^ lin(P.G, u)];
+    }
 }
 
 }  // namespace
 }  // namespace bmmc
 
 using namespace bmmc;
+
+extern "C" int bmmc_sortnet_passes(int n, int* passes_out, int* columns_out) {
+    if (n < 2 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [2, %d]", n, BMMC_MAX_BITS);
+    const std::vector<BitMat>* st = stages_for(n);
+    if (!st) return set_error(BMMC_ERR_INTERNAL, "network compilation failed for n = %d", n);
+    const std::vector<NetPass>* passes = nullptr;
+    int rc = passes_for(n, *st, &passes);
+    if (rc != BMMC_OK) return rc;
+    if (passes_out) *passes_out = (int)passes->size();
+    if (columns_out) {
+        int most = 0;
+        for (const NetPass& np : *passes) most = std::max(most, (int)np.cols.count);
+        *columns_out = most;
+    }
+    return BMMC_OK;
+}
+
+extern "C" int bmmc_sortnet_emulate(const void* in, void* out, int n, int key_type, int* passes_out) {
+    if (n < 2 || n > 24) return set_error(BMMC_ERR_RANGE, "emulation supports 2 <= n <= 24");
+    if (!in || !out) return set_error(BMMC_ERR_ARG, "in/out must not be NULL");
+    if (key_type != BMMC_KEY_I32 && key_type != BMMC_KEY_U32)
+        return set_error(BMMC_ERR_ARG, "key_type = %d is not a bmmc_key_type", key_type);
+    const std::vector<BitMat>* st = stages_for(n);
+    if (!st) return set_error(BMMC_ERR_INTERNAL, "network compilation failed for n = %d", n);
+    const std::vector<NetPass>* passes = nullptr;
+    int rc = passes_for(n, *st, &passes);
+    if (rc != BMMC_OK) return rc;
+    const size_t count = (size_t)1 << n;
+    std::vector<uint32_t> a((const uint32_t*)in, (const uint32_t*)in + count), b(count);
+    for (const NetPass& np : *passes) {
+        emulate_net_pass(np, key_type == BMMC_KEY_I32 ? 1 : 2, a.data(), b.data());
+        a.swap(b);
+    }
+    std::memcpy(out, a.data(), count * 4);
+    if (passes_out) *passes_out = (int)passes->size();
+    return BMMC_OK;
+}
 
 extern "C" int bmmc_sortnet_stages(int n, uint64_t* rows_out, int max_matrices, int* count_out) {
     if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);

@@ -51,6 +51,22 @@ struct BatchItem {
     uint32_t pad_;
 };
 
+// Columns of the sorting network done inside each tile, in LDS, between the
+// read and the write phase of a pass.  Column i pairs the slots s and
+// s XOR f; bit 0 of the index, in column i's own index space, of the element
+// at slot s is parity(beta & s) XOR parity(g & r), r the tile's coset
+// representative; of each pair, the element whose bit is 0 keeps the smaller
+// key.
+constexpr int kMaxNetCols = 96;
+struct NetCol {
+    uint32_t f, beta, g;
+};
+struct NetColumns {
+    uint32_t count;
+    uint32_t pad_[3];
+    NetCol col[kMaxNetCols];
+};
+
 // Per-pass device descriptor for the batched kernel.
 struct BatchPass {
     const void* in;

@@ -167,7 +167,7 @@ void general_runs(const KernelShape& ks, int* a, int* b) {
 }
 
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
-               uint64_t seed, PassPlan* p, int tb_mix, int iter_mix) {
+               uint64_t seed, PassPlan* p, int tb_mix, int iter_mix, const uint64_t* extra, int nextra) {
     const int n = T.n;
     const int D = ks.D();
     BitMat Ti;
@@ -221,6 +221,13 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
                 X[d++] = hs[i];
                 vb.insert(hs[i]);
             }
+        }
+        // Vectors the caller needs inside every tile.
+        for (int i = 0; i < nextra; i++) {
+            const uint64_t v = extra[i] & low_mask(n);
+            if (!vb.insert(v)) continue;
+            X[d++] = v;
+            if (popcount64(v) != 1) p->coordinate = false;
         }
         p->dim_v0 = d;
         if (d > D) return BMMC_ERR_RANGE;

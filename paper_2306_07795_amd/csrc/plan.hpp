@@ -78,10 +78,12 @@ inline bool is_tiled(const BitMat& A, int t) { return popcount64(tiled_row_mask(
 bool factorize_ulp(const BitMat& A, BitMat* U, BitMat* L, BitMat* P, BitMat* T1, BitMat* T2);
 
 // Geometry and tables of one pass out[T.x XOR c] = in[x] with read runs of
-// 2^a and write runs of 2^b elements, for the given kernel shape.
-// Returns 0 or a negative bmmc_status.
+// 2^a and write runs of 2^b elements, for the given kernel shape; the tile
+// subspace also contains the `nextra` input-space vectors `extra`.
+// Returns 0 or a negative bmmc_status (BMMC_ERR_RANGE: the tile would not fit).
 int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks, int swizzle,
-               uint64_t seed, PassPlan* out, int tb_mix = 0, int iter_mix = 0);
+               uint64_t seed, PassPlan* out, int tb_mix = 0, int iter_mix = 0,
+               const uint64_t* extra = nullptr, int nextra = 0);
 
 // Full plan for out[A.x XOR c] = in[x].
 int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions& opt, Plan* out);

@@ -154,19 +154,13 @@ LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double
             return;
         }
     }
+    hipEventRecord(pe.start, stream);
     ds->events.push_back(pe);
-    ev.start = pe.start;
-    ev.stop = pe.stop;
-}
-
-void LaunchScope::bracket() {
-    if (!ev.start) return;
-    hipEventRecord(ev.start, stream);
-    bracketed = true;
+    stop = pe.stop;
 }
 
 LaunchScope::~LaunchScope() {
-    if (bracketed) hipEventRecord(ev.stop, stream);
+    if (stop) hipEventRecord(stop, stream);
 }
 
 PlanOptions plan_options(const bmmc_options_t* o, int w) {
@@ -216,7 +210,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
     hipError_t e;
     if (plan.npass == 0) {
         LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
-        e = launch_copy(in, out, bytes, stream, 4, 0, ls.events());
+        e = launch_copy(in, out, bytes, stream);
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
     }
     if (plan.naive) {
@@ -226,7 +220,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         na.c = (uint32_t)plan.c;
         for (int j = 0; j < plan.n; j++) na.col[j] = (uint32_t)plan.A.col(j);
         LaunchScope ls(ds, stream, "k_naive", 2.0 * bytes);
-        e = launch_naive(plan.w, plan.n, in, out, na, stream, ls.events());
+        e = launch_naive(plan.w, plan.n, in, out, na, stream);
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "naive launch");
     }
     const KernelShape& ks = plan.shape;
@@ -247,7 +241,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         kernel_name(name, sizeof(name), plan, hints);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
         e = launch_tiled(plan.w, ks.nt, ks.iters, hints, src, dst, tab, ntiles, grid,
-                         (order & 1) ? (uint32_t)ds->xcds : 0u, stream, ls.events());
+                         (order & 1) ? (uint32_t)ds->xcds : 0u, stream);
         if (e != hipSuccess) return hip_fail(e, "tiled launch");
     }
     return BMMC_OK;
@@ -421,7 +415,7 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
     if (!ds) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
     LaunchScope ls(ds, (hipStream_t)stream, "k_copy", 2.0 * (double)bytes);
-    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints, ls.events());
+    hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
 }
 

@@ -61,18 +61,15 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
 // Scratch of at least `bytes` for `stream` (caller holds ds->mu).
 int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out);
 
-// Timing of one launch when profiling is on (caller holds ds->mu): events()
-// go to a kernel launcher, which has the launch itself update them; for work
-// that is not one kernel launch (a graph), bracket() records them around it.
+// Timing of one launch when profiling is on (caller holds ds->mu): events
+// recorded on the stream right before (constructor) and after (destructor)
+// the work enqueued in the scope.
 struct LaunchScope {
     DeviceState* ds;
     hipStream_t stream;
-    LaunchEv ev;  // null events when not profiling
-    bool bracketed = false;
+    hipEvent_t stop = nullptr;
     LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes);
     ~LaunchScope();
-    const LaunchEv& events() const { return ev; }
-    void bracket();
 };
 
 // Plan options from the public option struct.

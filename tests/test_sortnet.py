@@ -51,6 +51,25 @@ def test_compiled_network_sorts_on_the_cpu(n, signed):
     assert np.array_equal(x, O.sort_keys(a, signed))
 
 
+@pytest.mark.parametrize("signed", [True, False])
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 12, 13, 14, 16, 18])
+def test_fused_passes_sort_on_the_cpu(n, signed):
+    """The device passes (stages grouped, columns in LDS) emulated on the host
+    with the kernel's own tables: the oracle's sort, in far fewer passes than
+    columns, and in one pass while the array fits one tile."""
+    a = keys(n, 7 * n + signed)
+    out = np.zeros_like(a)
+    passes = B.bmmc_sortnet_emulate(a, out, n, B.KEY_I32 if signed else B.KEY_U32)
+    assert np.array_equal(out, O.sort_keys(a, signed))
+    assert B.bmmc_sortnet_passes(n)[0] == passes
+    columns = n * (n + 1) // 2
+    assert passes <= columns + 1
+    if n <= 13:
+        assert passes == 1
+    else:
+        assert passes < columns // 3
+
+
 def test_errors():
     with pytest.raises(B.BmmcError):
         B.bmmc_sortnet_stages(33)
