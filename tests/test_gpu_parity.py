@@ -232,3 +232,36 @@ def test_parm_split_and_merge_on_device():
         idx = np.nonzero(sub == s)[0]
         want[idx] = a[idx][::-1]
     assert np.array_equal(G.to_host(y, a), want)
+
+
+def test_permutes_captured_in_a_graph():
+    """Library calls captured into a HIP graph (through torch's capture on the
+    library's stream) and replayed with fresh inputs and eager work between
+    replays: every replay equals the oracle."""
+    n = 20
+    cases = [(gen.bit_reversal_rows(n), 0), gen.random_bmmc(n, 41)]
+    a = gen.data(n, 4, 0)
+    x = G.to_device(a)
+    ys = [G.empty_like_bytes(a) for _ in cases]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # plans made and kernels loaded before capture
+        for (rows, c), y in zip(cases, ys):
+            B.bmmc_permute(x, y, n, rows, c, 4, side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream()
+        for (rows, c), y in zip(cases, ys):
+            B.bmmc_permute(x, y, n, rows, c, 4, cap)
+    for rep in range(3):
+        a = gen.data(n, 4, 100 + rep)
+        x.copy_(torch.from_numpy(a.view(np.uint8)).to(G.dev()))
+        for y in ys:
+            y.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (rows, c), y in zip(cases, ys):
+            assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c)), rep
