@@ -309,10 +309,12 @@ int run_passes(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
 
 // Host emulation of one k_tiled_net pass with the same tables: tile by tile,
 // the read phase by X and F, the columns by f, beta and g, the write phase by
-// Y and G.
+// Y and G, each 16-byte vector addressed as the kernel addresses it (the
+// vector index from the coordinates above the element bits).
 void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* dst) {
     const PassTables& P = np.plan.tab;
     const uint32_t d = P.d, slots = 1u << d;
+    const uint32_t lv = d < 2 ? d : 2, em = (1u << lv) - 1u;  // 4-byte keys: 4 per vector
     std::vector<uint32_t> lds(slots);
     auto lin = [](const uint32_t* tab, uint32_t v) {
         uint32_t r = 0;
@@ -327,7 +329,10 @@ void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* 
                 yb ^= P.tb[j][1];
                 gx ^= P.tb[j][2];
             }
-        for (uint32_t v = 0; v < slots; v++) lds[lin(P.F, v)] = src[r ^ lin(P.X, v)];
+        for (uint32_t v = 0; v < slots; v++) {
+            const uint32_t x = r ^ lin(P.X, v & ~em);
+            lds[lin(P.F, v)] = src[(x & ~em) | (v & em)];
+        }
         for (uint32_t i = 0; i < np.cols.count; i++) {
             const NetCol& c = np.cols.col[i];
             const uint32_t p = __builtin_ctz(c.f), lo = (1u << p) - 1u;
@@ -343,7 +348,10 @@ void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* 
                 }
             }
         }
-        for (uint32_t u = 0; u < slots; u++) dst[yb ^ lin(P.Y, u)] = lds[gx ^ lin(P.G, u)];
+        for (uint32_t u = 0; u < slots; u++) {
+            const uint32_t y = yb ^ lin(P.Y, u & ~em);
+            dst[(y & ~em) | (u & em)] = lds[gx ^ lin(P.G, u)];
+        }
     }
 }
 

@@ -222,10 +222,12 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
                 vb.insert(hs[i]);
             }
         }
-        // Vectors the caller needs inside every tile.
+        // Vectors the caller needs inside every tile, taken modulo the low a
+        // input bits (already in the tile): a coordinate's input offset must
+        // keep the element bits of a 16-byte vector clear.
         for (int i = 0; i < nextra; i++) {
-            const uint64_t v = extra[i] & low_mask(n);
-            if (!vb.insert(v)) continue;
+            const uint64_t v = extra[i] & low_mask(n) & ~low_mask(a);
+            if (!v || !vb.insert(v)) continue;
             X[d++] = v;
             if (popcount64(v) != 1) p->coordinate = false;
         }
@@ -284,6 +286,11 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
         if (cc == ~0ull) return BMMC_ERR_INTERNAL;
         G0[k] = cc;
     }
+
+    // The kernels move 16-byte vectors: beyond the vector's own element
+    // bits, no read or write coordinate may touch them.
+    for (int k = ks.lv(); k < d; k++)
+        if ((X[k] | Y[k]) & low_mask(ks.lv())) return BMMC_ERR_INTERNAL;
 
     PassTables& tab = p->tab;
     std::memset(&tab, 0, sizeof(tab));
