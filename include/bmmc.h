@@ -135,7 +135,8 @@ typedef struct {
     int use_graph;      /* 0 or 1 (default): replay a captured hipGraph; -1: plain launches */
     int method;         /* bmmc_method for the arrays larger than a tile */
     int hints;          /* as bmmc_options_t.hints (0: non-temporal above 64 MiB moved) */
-    int reserved[2];
+    int iters;          /* 16-byte vectors per thread per tile: 4 (default, 16 KiB tiles) or 8 */
+    int reserved[1];
 } bmmc_batch_options_t;
 
 /* Per-kernel timing gathered between bmmc_profile_begin and _end. */

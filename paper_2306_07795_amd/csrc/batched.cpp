@@ -27,10 +27,10 @@ struct BatchState {
     void* host = nullptr;  // pinned staging of the same layout
     size_t cap_passes = 0, cap_items = 0;
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
-    // one captured graph per cache-hint setting (batches of different sizes
-    // alternate between them), each for one grid size
-    hipGraphExec_t exec[4] = {};
-    uint32_t exec_grid[4] = {};
+    // one captured graph per (cache hints, tile iterations) setting (batches
+    // of different sizes alternate between them), each for one grid size
+    hipGraphExec_t exec[8] = {};
+    uint32_t exec_grid[8] = {};
 };
 
 struct BatchRegistry {
@@ -107,19 +107,19 @@ BatchState* batch_state(hipStream_t stream, int device) {
 
 // Enqueue [clear heads] -> phase 0 -> phase 1 on `s` (captured or not) for
 // the device table at d with layout L.
-hipError_t enqueue_phases_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipStream_t s) {
+hipError_t enqueue_phases_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, hipStream_t s) {
     uint32_t* heads = (uint32_t*)(d + L.heads_off);
     const BatchPass* passes = (const BatchPass*)(d + L.passes_off);
     const BatchItem* items = (const BatchItem*)(d + L.items_off);
     const uint32_t* range = (const uint32_t*)d;
     hipError_t e = launch_zero(heads, 2, s);
-    if (e == hipSuccess) e = launch_batched(passes, items, range, 0, heads, grid, hints, s);
-    if (e == hipSuccess) e = launch_batched(passes, items, range, 1, heads + 1, grid, hints, s);
+    if (e == hipSuccess) e = launch_batched(passes, items, range, 0, heads, grid, hints, iters, s);
+    if (e == hipSuccess) e = launch_batched(passes, items, range, 1, heads + 1, grid, hints, iters, s);
     return e;
 }
 
 // Capture the three launches into an executable graph.
-int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipGraphExec_t* out) {
+int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, hipGraphExec_t* out) {
     hipStream_t cap;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -128,7 +128,7 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipG
         hipStreamDestroy(cap);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    enqueue_phases_at(d, L, grid, hints, cap);
+    enqueue_phases_at(d, L, grid, hints, iters, cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
     hipStreamDestroy(cap);
@@ -142,16 +142,17 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, hipG
     return BMMC_OK;
 }
 
-int build_graph(BatchState* bs, uint32_t grid, int hints) {
-    hipGraphExec_t& g = bs->exec[hints & 3];
-    if (g && bs->exec_grid[hints & 3] == grid) return BMMC_OK;
+int build_graph(BatchState* bs, uint32_t grid, int hints, int iters) {
+    const int slot = (hints & 3) | (iters == 8 ? 4 : 0);
+    hipGraphExec_t& g = bs->exec[slot];
+    if (g && bs->exec_grid[slot] == grid) return BMMC_OK;
     if (g) {
         hipGraphExecDestroy(g);
         g = nullptr;
     }
-    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, &g);
+    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, iters, &g);
     if (st != BMMC_OK) return st;
-    bs->exec_grid[hints & 3] = grid;
+    bs->exec_grid[slot] = grid;
     return BMMC_OK;
 }
 
@@ -280,14 +281,14 @@ int batch_validate(const bmmc_desc_t* descs, int count) {
 }
 
 
-int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out) {
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out) {
     PlanOptions po;
     po.method = (method == BMMC_METHOD_ONEPASS || method == BMMC_METHOD_TILED) ? method : kMethodAuto;
     if (d.elem_bytes >= 4) {
         // the batched kernel's one shape
         po.shape = default_shape(d.elem_bytes);
         po.shape.nt = batched_threads();
-        po.shape.iters = batched_iters();
+        po.shape.iters = batched_iters(iters);
         po.shape_given = true;
     }
     int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, po, &out->plan);
@@ -341,19 +342,20 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     if (!bs->staged) hipEventCreateWithFlags(&bs->staged, hipEventDisableTiming);
     hipEventRecord(bs->staged, stream);
 
+    const int iters = batched_iters(o.iters);
     const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
-                                           : (uint32_t)(ds->cu_count * batched_occupancy());
+                                           : (uint32_t)(ds->cu_count * batched_occupancy(iters));
     const int hints = resolve_batch_hints(o, moved);
     if (o.use_graph >= 0) {
-        st = build_graph(bs, grid, hints);
+        st = build_graph(bs, grid, hints, iters);
         if (st != BMMC_OK) return st;
     }
     LaunchScope ls(ds, stream, "k_batched", moved);
     if (o.use_graph >= 0) {
-        e = hipGraphLaunch(bs->exec[hints & 3], stream);
+        e = hipGraphLaunch(bs->exec[(hints & 3) | (iters == 8 ? 4 : 0)], stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, stream);
+        e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, iters, stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     return BMMC_OK;
@@ -385,19 +387,20 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     int st = batch_validate(descs, count);
     if (st != BMMC_OK) return st;
     if (count == 0) return BMMC_OK;
-    DeviceState* ds = device_state(&st);
-    if (!ds) return st;
-    hipStream_t stream = (hipStream_t)stream_;
     bmmc_batch_options_t o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    hipStream_t stream = (hipStream_t)stream_;
 
     std::vector<BatchArray> arrays(count);
     size_t scratch_total = 0;
     std::vector<size_t> offs(count, 0);
     for (int i = 0; i < count; i++) {
-        st = plan_batch_array(ds, descs[i], o.method, &arrays[i]);
+        st = plan_batch_array(ds, descs[i], o.method, o.iters, &arrays[i]);
         if (st != BMMC_OK) return set_error(st, "array %d: %s", i, bmmc_last_error());
         if (!arrays[i].single && arrays[i].plan->npass == 2) {
             offs[i] = scratch_total;
@@ -431,6 +434,7 @@ struct PreparedBatch {
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0;
     int hints = 0;
+    int iters = 4;
     bool use_graph = true;
     Layout L{};
     double moved = 0;
@@ -444,12 +448,13 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     int st = batch_validate(descs, count);
     if (st != BMMC_OK) return st;
     if (count == 0) return set_error(BMMC_ERR_ARG, "empty batch");
-    DeviceState* ds = device_state(&st);
-    if (!ds) return st;
     bmmc_batch_options_t o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
 
     auto* pb = new PreparedBatch();
@@ -458,7 +463,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     size_t scratch_total = 0;
     std::vector<size_t> offs(count, 0);
     for (int i = 0; i < count; i++) {
-        st = plan_batch_array(ds, descs[i], o.method, &pb->arrays[i]);
+        st = plan_batch_array(ds, descs[i], o.method, o.iters, &pb->arrays[i]);
         if (st != BMMC_OK) {
             delete pb;
             return set_error(st, "array %d: %s", i, bmmc_last_error());
@@ -500,11 +505,12 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     }
     e = hipMemcpy(pb->table, image.data(), pb->L.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy (batch table)"));
-    pb->grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy());
+    pb->iters = batched_iters(o.iters);
+    pb->grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(pb->iters));
     pb->hints = resolve_batch_hints(o, pb->moved);
     pb->use_graph = o.use_graph >= 0;
     if (!work.empty() && pb->use_graph) {
-        st = capture_graph_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, &pb->exec);
+        st = capture_graph_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters, &pb->exec);
         if (st != BMMC_OK) return fail(st);
     }
     *handle_out = pb;
@@ -527,7 +533,8 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     if (!any) return BMMC_OK;
     LaunchScope ls(ds, stream, "k_batched", pb->moved);
     hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
-                                 : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, stream);
+                                 : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters,
+                                                     stream);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "batch launch");
 }
 

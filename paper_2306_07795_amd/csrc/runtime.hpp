@@ -95,7 +95,7 @@ struct BatchArray {
 };
 
 int batch_validate(const bmmc_desc_t* descs, int count);
-int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out);
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out);
 // Enqueue one batched launch (caller holds ds->mu).
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream);

@@ -198,7 +198,7 @@ void Server::plan_loop() {
         to_plan.pop_front();
         lk.unlock();
         BatchArray ba;
-        int st = plan_batch_array(ds, r->desc, opt.method, &ba);
+        int st = plan_batch_array(ds, r->desc, opt.method, 0, &ba);
         lk.lock();
         if (st != BMMC_OK) {
             r->status = st;

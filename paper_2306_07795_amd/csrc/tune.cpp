@@ -57,8 +57,8 @@ int load_file(TuneCache& c, const char* path) {
         uint64_t sig;
         if (std::sscanf(line,
                         "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
-                        "\"order\": %d, \"method\": %d, \"ms\": %lf}",
-                        &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &ms) == 6) {
+                        "\"order\": %d, \"method\": %d, \"iters\": %d, \"ms\": %lf}",
+                        &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &b.iters, &ms) == 7) {
             c.batch[sig] = {b, ms};
             count++;
         }
@@ -92,8 +92,8 @@ int save_file(TuneCache& c, const char* path) {
         const bmmc_batch_options_t& b = kv.second.first;
         std::fprintf(f,
                      "{\"kind\": \"batch\", \"sig\": \"%016" PRIx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
-                     "\"order\": %d, \"method\": %d, \"ms\": %.6f}\n",
-                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, kv.second.second);
+                     "\"order\": %d, \"method\": %d, \"iters\": %d, \"ms\": %.6f}\n",
+                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, b.iters, kv.second.second);
     }
     std::fclose(f);
     return BMMC_OK;
@@ -331,38 +331,41 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     hipStream_t stream = (hipStream_t)stream_;
-    const int occ = batched_occupancy();
     static const int kChunks[] = {1, 2, 4, 8, 16};
     double best = 1e30;
     bmmc_batch_options_t bo;
     std::memset(&bo, 0, sizeof(bo));
     Timer tm;
     for (int method : {BMMC_METHOD_AUTO, BMMC_METHOD_TILED}) {
-        for (int chunk : kChunks) {
-            for (int order = 0; order < 2; order++) {
-                for (int g = 1; g <= 2; g++) {
-                    bmmc_batch_options_t o;
-                    std::memset(&o, 0, sizeof(o));
-                    o.method = method;
-                    o.chunk_tiles = chunk;
-                    o.order = order;
-                    o.workgroups = ds->cu_count * occ * g / 2;
-                    // time graph replays of a resident batch: device time only
-                    void* pb = nullptr;
-                    st = bmmc_batch_create(descs, count, &o, &pb);
-                    if (st != BMMC_OK) return st;
-                    bmmc_batch_launch(pb, stream);  // warm-up
-                    hipEventRecord(tm.a, stream);
-                    for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
-                    hipEventRecord(tm.b, stream);
-                    hipEventSynchronize(tm.b);
-                    bmmc_batch_destroy(pb);
-                    float ms = 0;
-                    hipEventElapsedTime(&ms, tm.a, tm.b);
-                    const double per = ms / reps;
-                    if (per < best) {
-                        best = per;
-                        bo = o;
+        for (int iters : {4, 8}) {
+            const int occ = batched_occupancy(iters);
+            for (int chunk : kChunks) {
+                for (int order = 0; order < 2; order++) {
+                    for (int g = 1; g <= 2; g++) {
+                        bmmc_batch_options_t o;
+                        std::memset(&o, 0, sizeof(o));
+                        o.method = method;
+                        o.iters = iters;
+                        o.chunk_tiles = chunk;
+                        o.order = order;
+                        o.workgroups = ds->cu_count * occ * g / 2;
+                        // time graph replays of a resident batch: device time only
+                        void* pb = nullptr;
+                        st = bmmc_batch_create(descs, count, &o, &pb);
+                        if (st != BMMC_OK) return st;
+                        bmmc_batch_launch(pb, stream);  // warm-up
+                        hipEventRecord(tm.a, stream);
+                        for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
+                        hipEventRecord(tm.b, stream);
+                        hipEventSynchronize(tm.b);
+                        bmmc_batch_destroy(pb);
+                        float ms = 0;
+                        hipEventElapsedTime(&ms, tm.a, tm.b);
+                        const double per = ms / reps;
+                        if (per < best) {
+                            best = per;
+                            bo = o;
+                        }
                     }
                 }
             }

@@ -53,11 +53,12 @@ def test_batched_mixed_sizes_and_widths(order, use_graph, hints, method):
     check_all(arrays)
 
 
+@pytest.mark.parametrize("iters", [4, 8])
 @pytest.mark.parametrize("chunk", [1, 4, 16])
-def test_batched_chunks_and_grid(chunk):
+def test_batched_chunks_and_grid(chunk, iters):
     sizes = gen.batched_sizes(40, chunk, 10, 20)
-    arrays = make_batch(sizes, [4] * len(sizes), chunk)
-    B.bmmc_permute_batched(items(arrays), G.stream(), {"chunk_tiles": chunk, "workgroups": 64})
+    arrays = make_batch(sizes, [4, 8, 16, 4] * (len(sizes) // 4), chunk)
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"chunk_tiles": chunk, "workgroups": 64, "iters": iters})
     G.sync()
     check_all(arrays)
 
@@ -86,8 +87,9 @@ def test_graph_replays_with_fresh_data():
         check_all(arrays)
 
 
+@pytest.mark.parametrize("iters", [4, 8])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
-def test_batch_of_1024_like_the_workload(method):
+def test_batch_of_1024_like_the_workload(method, iters):
     """1024 arrays, n uniform in [10, 22], int32, each with its own A and c
     (the batched workload's shape); every array checked on sampled outputs
     and the smallest hundred in full."""
@@ -98,7 +100,7 @@ def test_batch_of_1024_like_the_workload(method):
         a = gen.data(n, 4, k)
         arrays.append({"n": n, "w": 4, "rows": rows, "c": c, "a": a,
                        "x": G.to_device(a), "y": G.empty_like_bytes(a)})
-    B.bmmc_permute_batched(items(arrays), G.stream(), {"method": method})
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"method": method, "iters": iters})
     G.sync()
     rng = np.random.default_rng(0)
     order = sorted(range(len(arrays)), key=lambda k: arrays[k]["n"])
@@ -229,15 +231,16 @@ def test_server_budget_admission_and_caller_outputs(method):
         B.bmmc_server_destroy(srv)
 
 
+@pytest.mark.parametrize("iters", [4, 8])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
-def test_prepared_batch_replays(method):
+def test_prepared_batch_replays(method, iters):
     """A resident batch (plans, table, scratch and graph made once) replayed
     with fresh inputs each time; every array checked each time."""
     rng = np.random.default_rng(31)
     sizes = [int(v) for v in rng.integers(0, 21, size=40)]
     widths = [int(v) for v in rng.choice([4, 8, 16, 2], size=40)]
     arrays = make_batch(sizes, widths, 31)
-    pb = B.bmmc_batch_create(items(arrays), {"method": method})
+    pb = B.bmmc_batch_create(items(arrays), {"method": method, "iters": iters})
     try:
         for rep in range(3):
             for k, ar in enumerate(arrays):
