@@ -265,3 +265,28 @@ def test_permutes_captured_in_a_graph():
         torch.cuda.synchronize()
         for (rows, c), y in zip(cases, ys):
             assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c)), rep
+
+
+@pytest.mark.parametrize("n,w,method", [(32, 1, B.METHOD_AUTO), (32, 1, B.METHOD_TILED),
+                                        (30, 4, B.METHOD_AUTO), (29, 8, B.METHOD_TILED)])
+def test_maximum_sizes_sampled(n, w, method):
+    """The largest index space (n = 32, 2^32 one-byte elements) and 4 GiB
+    arrays of wider elements: 65536 sampled outputs, the first and last
+    indices among them, against the oracle's index map."""
+    print(f"max size n={n} w={w} method={method}", flush=True)
+    rows, c = gen.random_bmmc(n, 3200 + n)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(n * 10 + w)
+    x = torch.randint(0, 256, ((1 << n) * w,), dtype=torch.uint8, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    B.bmmc_permute_ex(x, y, n, rows, c, w, {"method": method}, G.stream())
+    G.sync()
+    rng = np.random.default_rng(n)
+    xs = rng.integers(0, 1 << n, size=1 << 16, dtype=np.uint64)
+    xs[:4] = [0, 1, (1 << n) - 2, (1 << n) - 1]
+    ys = O.apply_many(rows, c, n, xs)
+    xi = torch.from_numpy(xs.astype(np.int64)).to(G.dev())
+    yi = torch.from_numpy(ys.astype(np.int64)).to(G.dev())
+    assert torch.equal(y.view(-1, w)[yi], x.view(-1, w)[xi])
+    del x, y
+    torch.cuda.empty_cache()
