@@ -31,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "BMMC permute GB/s (rd+wr) as % of device copy & HBM peak; batched p99 latency"
+# Autotuner results for this GPU model (JSON lines of the library's tuning
+# cache): loaded unless --retune, written by --save-tune.
+TUNE_DB = os.path.join(ROOT, "paper_2306_07795_amd", "tuning", "mi355x.jsonl")
 HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {
@@ -172,7 +175,7 @@ def best_device_copy(x, y, nbytes, stream):
     return best
 
 
-def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True):
+def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True, retune=False):
     """The paper's scheme on the same input: the factorization into tiled
     BMMCs, two LDS-staged passes through scratch (Section 5.2), tuned the
     same way; with its dominant kernel's per-launch rate."""
@@ -180,8 +183,11 @@ def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True):
     nbytes = (1 << n) * w
     opts = {"method": B.METHOD_TILED}
     if tune:
-        opts, _ = B.bmmc_autotune(n, w, B.METHOD_TILED, stream, 3)
-        opts = B.bmmc_tune_lookup(n, w, rows, B.METHOD_TILED) or opts
+        found = None if retune else B.bmmc_tune_lookup(n, w, rows, B.METHOD_TILED)
+        if found is None:
+            B.bmmc_autotune(n, w, B.METHOD_TILED, stream, 3)
+            found = B.bmmc_tune_lookup(n, w, rows, B.METHOD_TILED)
+        opts = found or opts
     passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
     for _ in range(3):
         B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
@@ -203,7 +209,7 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
-def bench_batched(count=1024, reps=50, seed=0):
+def bench_batched(count=1024, reps=50, seed=0, retune=False):
     """1024 arrays, n uniform in [10, 22], int32, each its own A and c: one
     graph-launched persistent kernel against 1024 separate bmmc_permute calls
     on one stream.  Batch latency = one launch's events; p50/p99 over reps."""
@@ -220,7 +226,9 @@ def bench_batched(count=1024, reps=50, seed=0):
         items.append((x, y, n, 4, rows, c))
         total += (1 << n) * 4
     stream = torch.cuda.current_stream()
-    tuned, tune_ms = B.bmmc_autotune_batched(items, stream, 2)
+    tuned = None if retune else B.bmmc_tune_lookup_batched(items)
+    if tuned is None:
+        tuned, _ = B.bmmc_autotune_batched(items, stream, 2)
 
     def lat(fn, r):
         out = []
@@ -370,37 +378,48 @@ def sortnet_table(sizes=(12, 16, 20, 24, 26), seed=0):
 CACHE_RESIDENT_BYTES = 64 << 20
 
 
-def graph_timed_line(args, n, w, rows, c, opts, tuned, desc, x, y, nbytes, passes, stream):
-    """Arrays that stay in the caches run for a few microseconds, less than
-    what one host call costs: the `steps` calls are captured once into a HIP
-    graph (through torch's graph capture on the library's stream) and the
-    timed region is one replay of it.  The per-launch duration is the replay
-    time divided by the launches in it."""
+def graph_time(fn, steps, warmup):
+    """Mean time of fn() when `steps` calls are captured once into a HIP graph
+    (torch's capture; the calls enqueue on the capture stream) and the timed
+    region is one replay of it."""
     import torch
-    from paper_2306_07795_amd import binding as B
-    g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        for _ in range(args.warmup):
-            B.bmmc_permute_ex(x, y, n, rows, c, w, opts, side)
+        for _ in range(warmup):
+            fn(side)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         cap = torch.cuda.current_stream()
-        for _ in range(args.steps):
-            B.bmmc_permute_ex(x, y, n, rows, c, w, opts, cap)
+        for _ in range(steps):
+            fn(cap)
     g.replay()  # warm replay
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     g.replay()
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    return ev0.elapsed_time(ev1) / steps
+
+
+def graph_timed_line(args, n, w, rows, c, opts, tuned, desc, x, y, nbytes, passes, stream):
+    """Arrays that stay in the caches run for a few microseconds, less than
+    what one host call costs: the steps, and the copy they are compared with,
+    are timed as one replay of a graph of the calls.  The per-launch duration
+    is the replay time divided by the launches in it."""
+    from paper_2306_07795_amd import binding as B
+    ms = graph_time(lambda s: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, s), args.steps, args.warmup)
     value = gbps(nbytes, ms)
-    copy_ms, copy_how = best_device_copy(x, y, nbytes, stream)
+    copy_ms, copy_how = 1e30, None
+    for vpt in (1, 2, 4, 8):
+        for hints in (0, 1, 2, 3):
+            t = graph_time(lambda s: B.bmmc_copy_ex(x, y, nbytes, vpt, hints, s), args.steps, 2)
+            copy_ms, copy_how = min((copy_ms, copy_how), (t, f"k_copy vpt={vpt} hints={hints} (graph)"))
     dev_copy = gbps(nbytes, copy_ms)
     per_launch_ms = ms / passes
     achieved = 2.0 * nbytes / (per_launch_ms * 1e-3) / 1e9
@@ -429,6 +448,10 @@ def main():
     ap.add_argument("--workload", default="random26", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="auto", choices=["auto", "tiled", "onepass", "naive"])
     ap.add_argument("--no-tune", action="store_true", help="time the library defaults, no autotuning")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune now instead of taking the options from the tuning file")
+    ap.add_argument("--save-tune", metavar="PATH",
+                    help="merge this run's tuning into the JSON-lines file PATH")
     ap.add_argument("--options-from", metavar="BENCH_JSON",
                     help="no autotuning: take the options from the JSON line of an earlier run")
     ap.add_argument("--no-extras", action="store_true",
@@ -487,16 +510,22 @@ def main():
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
 
+    if args.save_tune and os.path.exists(args.save_tune):
+        B.bmmc_tune_load(args.save_tune)
+    elif not (args.retune or args.no_tune) and os.path.exists(TUNE_DB):
+        B.bmmc_tune_load(TUNE_DB)
     opts = {"method": method}
-    tuned = None
+    tuned, tuning = None, "library defaults"
     if args.options_from:
         with open(args.options_from) as fh:
             tuned = json.loads(fh.read().strip().splitlines()[-1])["config"]["options"]
+        tuning = "options of an earlier run"
     elif not args.no_tune and method != B.METHOD_NAIVE:
-        tuned, _ = B.bmmc_autotune(n, w, method, stream, 3)
-        if method == B.METHOD_AUTO:
-            # the tuned options of this matrix's class (tiled or not)
-            tuned = B.bmmc_tune_lookup(n, w, rows) or tuned
+        # the tuned options of this matrix's class (tiled or not)
+        tuned, tuning = (None if args.retune else B.bmmc_tune_lookup(n, w, rows, method)), "tuning file"
+        if tuned is None:
+            B.bmmc_autotune(n, w, method, stream, 3)
+            tuned, tuning = B.bmmc_tune_lookup(n, w, rows, method), "autotuned in this run"
     if tuned:
         opts = dict(tuned)
     passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
@@ -517,7 +546,10 @@ def main():
     del z
 
     if nbytes < CACHE_RESIDENT_BYTES:
-        return graph_timed_line(args, n, w, rows, c, opts, tuned, desc, x, y, nbytes, passes, stream)
+        graph_timed_line(args, n, w, rows, c, opts, tuned, desc, x, y, nbytes, passes, stream)
+        if args.save_tune:
+            B.bmmc_tune_save(args.save_tune)
+        return
 
     # timed region: exactly `steps` permutations, per-launch events on the stream
     for _ in range(args.warmup):
@@ -545,7 +577,8 @@ def main():
         naive_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, c, w, stream), 10, 2, stream)
         extras["naive_GBps"] = round(gbps(nbytes, naive_ms), 1)
         extras["paper_two_pass"] = paper_two_pass(x, y, n, rows, c, w, stream, dev_copy,
-                                                  tune=not (args.no_tune or args.options_from))
+                                                  tune=not (args.no_tune or args.options_from),
+                                                  retune=args.retune)
 
     # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
     dname, d = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
@@ -567,7 +600,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "elem_bytes": w, "method": args.method,
-                   "passes": passes, "seed": 0, "options": tuned},
+                   "passes": passes, "seed": 0, "options": tuned, "tuning": tuning},
         "pct_of_device_copy": round(100.0 * value / dev_copy, 2),
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
         "device_copy_GBps": round(dev_copy, 1),
@@ -579,7 +612,7 @@ def main():
     del x, y
     torch.cuda.empty_cache()
     if not args.no_batched and not args.no_extras:
-        line["batched"] = bench_batched()
+        line["batched"] = bench_batched(retune=args.retune)
         torch.cuda.empty_cache()
     if not args.no_served and not args.no_extras:
         line["served"] = bench_served(args.served_rate, args.served_seconds)
@@ -589,6 +622,8 @@ def main():
     if args.extras_out:
         with open(args.extras_out, "w") as f:
             json.dump({"kernels": kstats, **extras}, f, indent=1)
+    if args.save_tune:
+        B.bmmc_tune_save(args.save_tune)
     print(json.dumps(line), flush=True)
 
 

@@ -363,6 +363,12 @@ int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows, 
 int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* stream, int reps,
                           bmmc_batch_options_t* best_out, double* best_ms);
 
+/* The tuned batch options for batches with this histogram of (n, width):
+   returns 1 and fills *opts_out when the cache holds an entry, else 0.
+   These are the options bmmc_permute_batched and bmmc_batch_create use when
+   given none.  Host only.  Errors: _ARG. */
+int bmmc_tune_lookup_batched(const bmmc_desc_t* descs, int count, bmmc_batch_options_t* opts_out);
+
 /* Save / load the tuning cache as JSON lines.  BMMC_TUNE_CACHE, when set,
    names a file loaded on first use and rewritten after each tuning run.
    bmmc_tune_load returns the number of entries read. */

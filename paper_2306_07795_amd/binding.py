@@ -130,6 +130,7 @@ def lib():
         "bmmc_autotune": (_i32, [_i32, _i32, _i32, _vp, _i32, P(Options), P(_dbl)]),
         "bmmc_tune_save": (_i32, [_c.c_char_p]),
         "bmmc_tune_lookup": (_i32, [_i32, _i32, _i32, P(_u64), P(Options)]),
+        "bmmc_tune_lookup_batched": (_i32, [P(Desc), _i32, P(BatchOptions)]),
         "bmmc_tune_load": (_i32, [_c.c_char_p]),
         "bmmc_server_create": (_i32, [P(ServerOptions), P(_vp)]),
         "bmmc_server_destroy": (_i32, [_vp]),
@@ -159,7 +160,7 @@ def exported_names():
         "bmmc_tune_save", "bmmc_tune_load", "bmmc_server_create", "bmmc_server_destroy",
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
-        "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes",
+        "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes", "bmmc_tune_lookup_batched",
     ]
 
 
@@ -456,6 +457,18 @@ def bmmc_tune_lookup(n: int, elem_bytes: int, A_rows, method: int = METHOD_AUTO)
     if r == 0:
         return None
     return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
+
+
+def bmmc_tune_lookup_batched(items):
+    """The tuned batch options for batches of this size histogram (dict), or
+    None."""
+    arr, keep, count = make_descs(items)
+    o = BatchOptions()
+    r = _check(lib().bmmc_tune_lookup_batched(arr, count, _c.byref(o)))
+    del keep
+    if r == 0:
+        return None
+    return {f: getattr(o, f) for f, _ in BatchOptions._fields_ if f != "reserved"}
 
 
 def bmmc_autotune_batched(items, stream=None, reps: int = 3):

@@ -192,6 +192,11 @@ extern "C" int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_
     return tuned_options(n, elem_bytes, method, matrix_class(A_rows, n), opts_out) ? 1 : 0;
 }
 
+extern "C" int bmmc_tune_lookup_batched(const bmmc_desc_t* descs, int count, bmmc_batch_options_t* opts_out) {
+    if (!opts_out || count < 0 || (count > 0 && !descs)) return set_error(BMMC_ERR_ARG, "NULL argument");
+    return tuned_batch_options(batch_signature(descs, count), opts_out) ? 1 : 0;
+}
+
 extern "C" int bmmc_tune_save(const char* path) {
     if (!path) return set_error(BMMC_ERR_ARG, "path is NULL");
     TuneCache& c = cache();
