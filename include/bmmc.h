@@ -429,6 +429,11 @@ int bmmc_server_drain(void* handle);
 
 int bmmc_server_stats(void* handle, bmmc_server_stats_t* stats);
 
+/* Start the statistics afresh (counts, latencies, busy time; the peak
+   restarts from the bytes in use), e.g. after a warm-up.  Requests still in
+   flight count toward the new statistics when they finish. */
+int bmmc_server_reset_stats(void* handle);
+
 /* Stop the server threads, wait for its streams and free its memory. */
 int bmmc_server_destroy(void* handle);
 

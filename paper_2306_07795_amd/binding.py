@@ -140,6 +140,7 @@ def lib():
         "bmmc_server_drain": (_i32, [_vp]),
         "bmmc_server_stats": (_i32, [_vp, P(ServerStats)]),
         "bmmc_server_now_ns": (_i64, []),
+        "bmmc_server_reset_stats": (_i32, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -161,6 +162,7 @@ def exported_names():
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
         "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes", "bmmc_tune_lookup_batched",
+        "bmmc_server_reset_stats",
     ]
 
 
@@ -503,6 +505,10 @@ def bmmc_server_create(budget_bytes: int, streams: int = 4, max_batch: int = 0,
     h = _vp()
     _check(lib().bmmc_server_create(_c.byref(o), _c.byref(h)))
     return h.value
+
+
+def bmmc_server_reset_stats(handle):
+    _check(lib().bmmc_server_reset_stats(handle))
 
 
 def bmmc_server_destroy(handle):

@@ -483,6 +483,19 @@ extern "C" int bmmc_server_stats(void* handle, bmmc_server_stats_t* out) {
     return BMMC_OK;
 }
 
+extern "C" int bmmc_server_reset_stats(void* handle) {
+    Server* s = (Server*)handle;
+    if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->submitted = s->completed = s->rejected = s->batches = 0;
+    s->bytes_moved = s->batch_reqs = 0;
+    s->first_arrival = -1;
+    s->last_done = 0;
+    s->latencies_ms.clear();
+    s->peak = s->in_use;
+    return BMMC_OK;
+}
+
 extern "C" int bmmc_server_destroy(void* handle) {
     Server* s = (Server*)handle;
     if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
