@@ -253,3 +253,31 @@ def test_prepared_batch_replays(method, iters):
             check_all(arrays)
     finally:
         pb.close()
+
+
+def test_server_stats_reset_after_warm_up():
+    n, w = 16, 4
+    srv = B.bmmc_server_create(1 << 28, streams=2, own_outputs=True)
+    try:
+        a = gen.data(n, w, 90)
+        x = G.to_device(a)
+        torch.cuda.synchronize()
+        for k in range(3):
+            rows, c = gen.random_bmmc(n, 90 + k)
+            B.bmmc_server_submit(srv, x, 0, n, rows, c, w)
+        B.bmmc_server_drain(srv)
+        assert B.bmmc_server_stats(srv)["completed"] == 3
+        B.bmmc_server_reset_stats(srv)
+        st = B.bmmc_server_stats(srv)
+        assert st["completed"] == 0 and st["p99_ms"] == 0
+        rows, c = gen.random_bmmc(n, 99)
+        tk = B.bmmc_server_submit(srv, x, 0, n, rows, c, w)
+        done, out = B.bmmc_server_poll(srv, tk, wait=True)
+        y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+        B.bmmc_copy(out, y, a.nbytes, G.stream())
+        G.sync()
+        assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
+        B.bmmc_server_drain(srv)
+        assert B.bmmc_server_stats(srv)["completed"] == 1
+    finally:
+        B.bmmc_server_destroy(srv)
