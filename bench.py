@@ -189,14 +189,15 @@ def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True, retune=Fals
             found = B.bmmc_tune_lookup(n, w, rows, B.METHOD_TILED)
         opts = found or opts
     passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
-    for _ in range(3):
+    ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 3, stream)
+    B.bmmc_profile_begin()
+    for _ in range(20):
         B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
     torch_sync()
-    B.bmmc_profile_begin()
-    ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 0, stream)
     ks = B.bmmc_profile_end()
     kname, k = max(ks.items(), key=lambda kv: kv[1]["total_ms"])
-    per_launch = k["total_ms"] / k["launches"]
+    # both passes are the same kernel: the time per launch of the plain loop
+    per_launch = ms * 20 / k["launches"] if len(ks) == 1 else k["total_ms"] / k["launches"]
     v = gbps(nbytes, ms)
     return {"GBps": round(v, 1), "passes": passes, "pct_of_device_copy": round(100.0 * v / dev_copy, 2),
             "traffic_pct_of_device_copy": round(100.0 * v * passes / dev_copy, 2),
@@ -562,11 +563,12 @@ def main():
             B.bmmc_tune_save(args.save_tune)
         return
 
-    # timed region: exactly `steps` permutations, per-launch events on the stream
+    # timed region: exactly `steps` permutations, HIP events on the stream at
+    # its two ends only (events around every launch would add their own
+    # commands between the kernels: about 7 us per step here)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    B.bmmc_profile_begin()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -574,9 +576,15 @@ def main():
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
-    kstats = B.bmmc_profile_end()
     ms = ev0.elapsed_time(ev1) / args.steps
     value = gbps(nbytes, ms)
+    # which kernels a step launches, and each launch's own duration: the same
+    # steps again with events around every launch
+    B.bmmc_profile_begin()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kstats = B.bmmc_profile_end()
 
     # bounds in the same session
     copy_ms, copy_how = best_device_copy(x, y, nbytes, stream)
@@ -591,9 +599,14 @@ def main():
                                                   tune=not (args.no_tune or args.options_from),
                                                   retune=args.retune)
 
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    # roofline of the dominant kernel: algorithmic bytes per launch / mean
+    # launch time.  When every launch of a step is that kernel, the mean
+    # launch time is the timed region's time per launch (dispatch gaps
+    # included); otherwise the per-launch events give it.
     dname, d = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
-    per_launch_ms = d["total_ms"] / d["launches"]
+    events_ms = d["total_ms"] / d["launches"]
+    launches_per_step = d["launches"] / args.steps
+    per_launch_ms = ms / launches_per_step if len(kstats) == 1 else events_ms
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
     tbytes = traffic_for(dname)
@@ -603,6 +616,8 @@ def main():
                 "traffic": None if tbytes is None else round(tbytes / (per_launch_ms * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": tbytes,
                 "kernel": dname, "launches": d["launches"], "mean_launch_ms": round(per_launch_ms, 5),
+                "mean_launch_ms_events": round(events_ms, 5),
+                "launch_time_from": "timed region / launches" if len(kstats) == 1 else "per-launch events",
                 "bytes_per_launch": launch_bytes}
 
     line = {
