@@ -244,9 +244,17 @@ double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, 
 void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with_tiled,
                    const std::vector<TuneMatrix>& mats, const void* in, void* out, hipStream_t stream, int reps,
                    bmmc_options_t* bo, double* best) {
-    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}};
+    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}, {1024, 4}, {256, 16}};
     std::vector<std::pair<double, bmmc_options_t>> timed;
     Timer tm;
+    const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
+    // non-temporal stores (2) or loads and stores (3) beyond the last-level
+    // cache, none (4) or stores only below it
+    const int hint_set[2][2] = {{4, 2}, {2, 3}};
+    const int* hints_of = hint_set[bytes >= ((size_t)64 << 20) ? 1 : 0];
+    // runs of at least one 128-byte line on both sides
+    int min_run = 7;
+    for (int w = elem_bytes; w > 1; w >>= 1) min_run--;
     for (auto& sh : kShapes) {
         if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
         KernelShape ks = default_shape(elem_bytes);
@@ -254,30 +262,31 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
         ks.iters = sh[1];
         const int D = ks.D();
         const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters, 0);
-        const int h = D / 2;
-        // (read-run, write-run) bits: square, and one bit longer on either side
-        const int runs[][2] = {{h, h}, {D - h, h}, {h, D - h}, {h + 1, D - h - 1}, {D - h - 1, h + 1}};
-        for (auto& ab : runs) {
-            if (ab[0] < ks.lv() || ab[1] < ks.lv()) continue;
-            for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
-                for (int hints : {4, 2, 3}) {
-                    for (int order : {4, 2, 10}) {
-                        for (int g = 0; g < 2; g++) {
-                            bmmc_options_t o;
-                            std::memset(&o, 0, sizeof(o));
-                            // auto also tries the paper's two-pass scheme
-                            o.method = m == 0 ? method : BMMC_METHOD_TILED;
-                            o.t = ab[0] < ab[1] ? ab[0] : ab[1];
-                            o.run_in = ab[0];
-                            o.run_out = ab[1];
-                            o.threads = ks.nt;
-                            o.iters = ks.iters;
-                            o.swizzle = 1;
-                            o.hints = hints;
-                            o.tile_order = order;
-                            o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
-                            const double t = time_options(n, elem_bytes, mats, o, in, out, stream, reps, tm);
-                            if (t > 0) timed.push_back({t, o});  // else: shape does not fit this size
+        const int lo = min_run > ks.lv() ? min_run : ks.lv();
+        // (read-run, write-run) bits filling the tile, or all but one bit of it
+        for (int sum = D; sum >= D - 1; sum--) {
+            for (int a = lo; sum - a >= lo; a++) {
+                const int b = sum - a;
+                for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
+                    for (int hi = 0; hi < 2; hi++) {
+                        for (int order : {4, 2, 10, 3, 11}) {
+                            for (int g = 0; g < 2; g++) {
+                                bmmc_options_t o;
+                                std::memset(&o, 0, sizeof(o));
+                                // auto also tries the paper's two-pass scheme
+                                o.method = m == 0 ? method : BMMC_METHOD_TILED;
+                                o.t = a < b ? a : b;
+                                o.run_in = a;
+                                o.run_out = b;
+                                o.threads = ks.nt;
+                                o.iters = ks.iters;
+                                o.swizzle = 1;
+                                o.hints = hints_of[hi];
+                                o.tile_order = order;
+                                o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
+                                const double t = time_options(n, elem_bytes, mats, o, in, out, stream, reps, tm);
+                                if (t > 0) timed.push_back({t, o});  // else: shape does not fit this size
+                            }
                         }
                     }
                 }
