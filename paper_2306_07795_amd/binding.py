@@ -352,11 +352,21 @@ def bmmc_copy_ex(inp, out, nbytes: int, vpt: int = 4, hints: int = 0, stream=Non
     _check(lib().bmmc_copy_ex(_ptr(inp), _ptr(out), nbytes, vpt, hints, _stream(stream)))
 
 
+class DescBatch:
+    """The descriptors of a batch marshalled once, for repeated calls (every
+    batched entry point accepts one in place of the list of items)."""
+
+    def __init__(self, items):
+        self.arr, self.keep, self.count = make_descs(items)
+
+
 def make_descs(items):
-    """items: iterable of (in, out, n, elem_bytes, A_rows, c).  Returns a
-    ctypes array of Desc plus the row storage it points into (keep both
-    alive) and the count.  All rows go into one uint64 buffer."""
+    """items: iterable of (in, out, n, elem_bytes, A_rows, c), or a DescBatch.
+    Returns a ctypes array of Desc plus the row storage it points into (keep
+    both alive) and the count.  All rows go into one uint64 buffer."""
     import numpy as np
+    if isinstance(items, DescBatch):
+        return items.arr, items.keep, items.count
     items = list(items)
     count = len(items)
     arr = (Desc * max(count, 1))()

@@ -210,7 +210,10 @@ void Server::plan_loop() {
         }
         r->plan = ba.plan;
         r->state = kPlanned;
-        ready.push_back(r);
+        // planners finish out of order: keep `ready` in arrival order
+        auto at = ready.end();
+        while (at != ready.begin() && (*(at - 1))->arrival_ns > r->arrival_ns) --at;
+        ready.insert(at, r);
         cv_work.notify_all();
     }
 }
