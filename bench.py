@@ -328,6 +328,8 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0):
         "offered_GBps": round(2.0 * offered / (reqs[-1]["arrival"]) / 1e9, 1),
         "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
         "mean_batch": round(st["mean_batch"], 1), "launches": st["batches"],
+        "mean_plan_ms": round(st["mean_plan_ms"], 3), "mean_wait_ms": round(st["mean_wait_ms"], 3),
+        "mean_run_ms": round(st["mean_run_ms"], 3),
         "peak_budget_GB": round(st["peak_bytes"] / 1e9, 2),
     }
 

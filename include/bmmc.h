@@ -396,7 +396,11 @@ typedef struct {
     double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival-to-completion latency */
     int64_t in_use_bytes, peak_bytes;
     double mean_batch;    /* requests per launch */
-    double reserved[4];
+    /* mean of each stage of a completed request's latency: arrival to
+       planned, planned to launched (admission and a free stream), launched to
+       completion seen by the server */
+    double mean_plan_ms, mean_wait_ms, mean_run_ms;
+    double reserved[1];
 } bmmc_server_stats_t;
 
 /* A continuous-batching server on the current device.  It allocates one

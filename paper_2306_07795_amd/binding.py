@@ -76,7 +76,8 @@ class ServerStats(_c.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("batches", _i64),
                 ("bytes_moved", _dbl), ("busy_s", _dbl), ("p50_ms", _dbl), ("p99_ms", _dbl),
                 ("mean_ms", _dbl), ("max_ms", _dbl), ("in_use_bytes", _i64), ("peak_bytes", _i64),
-                ("mean_batch", _dbl), ("reserved", _dbl * 4)]
+                ("mean_batch", _dbl), ("mean_plan_ms", _dbl), ("mean_wait_ms", _dbl), ("mean_run_ms", _dbl),
+                ("reserved", _dbl * 1)]
 
 
 class ServerOptions(_c.Structure):

@@ -94,6 +94,7 @@ struct Request {
     bmmc_desc_t desc{};
     uint64_t rows[64] = {};
     int64_t arrival_ns = 0;
+    int64_t planned_ns = 0, launched_ns = 0;
     int64_t done_ns = 0;
     std::shared_ptr<const Plan> plan;
     size_t bytes = 0;
@@ -143,6 +144,7 @@ struct Server {
     double bytes_moved = 0, batch_reqs = 0;
     int64_t first_arrival = -1, last_done = 0;
     std::vector<double> latencies_ms;
+    double plan_ms = 0, wait_ms = 0, run_ms = 0;  // sums over completed requests
 
     void plan_loop();
     void dispatch_loop();
@@ -210,6 +212,7 @@ void Server::plan_loop() {
         }
         r->plan = ba.plan;
         r->state = kPlanned;
+        r->planned_ns = now_ns();
         // planners finish out of order: keep `ready` in arrival order
         auto at = ready.end();
         while (at != ready.begin() && (*(at - 1))->arrival_ns > r->arrival_ns) --at;
@@ -224,6 +227,9 @@ void Server::finish_slot(Slot& s, int64_t t) {
         r->state = kDone;
         const double lat = (double)(t - r->arrival_ns) * 1e-6;
         latencies_ms.push_back(lat);
+        plan_ms += (double)(r->planned_ns - r->arrival_ns) * 1e-6;
+        wait_ms += (double)(r->launched_ns - r->planned_ns) * 1e-6;
+        run_ms += (double)(t - r->launched_ns) * 1e-6;
         completed++;
         bytes_moved += 2.0 * (double)r->bytes;
         last_done = std::max(last_done, t);
@@ -285,6 +291,7 @@ void Server::dispatch_loop() {
                     ba.plan = r->plan;
                     ba.single = r->plan->npass == 0 || r->plan->naive || r->desc.elem_bytes < 4;
                     r->state = kRunning;
+                    r->launched_ns = now_ns();
                     s.reqs.push_back(r);
                 }
                 admitted.erase(admitted.begin(), admitted.begin() + take);
@@ -469,6 +476,11 @@ extern "C" int bmmc_server_stats(void* handle, bmmc_server_stats_t* out) {
     out->in_use_bytes = s->in_use;
     out->peak_bytes = s->peak;
     out->mean_batch = s->batches ? s->batch_reqs / (double)s->batches : 0.0;
+    if (s->completed) {
+        out->mean_plan_ms = s->plan_ms / (double)s->completed;
+        out->mean_wait_ms = s->wait_ms / (double)s->completed;
+        out->mean_run_ms = s->run_ms / (double)s->completed;
+    }
     std::vector<double> v = s->latencies_ms;
     if (!v.empty()) {
         std::sort(v.begin(), v.end());
@@ -495,6 +507,7 @@ extern "C" int bmmc_server_reset_stats(void* handle) {
     s->first_arrival = -1;
     s->last_done = 0;
     s->latencies_ms.clear();
+    s->plan_ms = s->wait_ms = s->run_ms = 0;
     s->peak = s->in_use;
     return BMMC_OK;
 }
