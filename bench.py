@@ -282,7 +282,7 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     }
 
 
-def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0):
+def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0):
     """Open-loop Poisson arrivals at `rate` requests/s for `seconds`: n uniform
     in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs resident in
     a pool per (n, width); outputs and scratch from the server's HBM budget.
@@ -300,7 +300,7 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0):
     for r in reqs:
         mats[r["id"]] = gen.random_bmmc(r["n"], r["seed"])
     torch.cuda.synchronize()
-    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2)
+    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2, use_graph=use_graph)
     try:
         # warm-up: a quarter second of the same stream (other matrices), then
         # the statistics start afresh
@@ -503,7 +503,8 @@ def main():
         print(json.dumps(sortnet_table()), flush=True)
         return
     if args.served_sweep:
-        rows = [bench_served(rate, args.served_seconds) for rate in (5000.0, 10000.0, 15000.0, 20000.0)]
+        rows = [dict(bench_served(rate, args.served_seconds, use_graph=g), use_graph=g)
+                for g in (0, 1) for rate in (5000.0, 10000.0, 15000.0, 20000.0)]
         print(json.dumps({"workload": "served load sweep", "table": rows}), flush=True)
         return
     if args.traffic_from:

@@ -386,7 +386,11 @@ typedef struct {
        is dropped at completion and the ticket forgotten (load generation). */
     int own_outputs;
     int method;           /* bmmc_method for two-pass-sized arrays */
-    int reserved[4];
+    /* 0 (default): each launch is plain launches of the batched kernel with
+       no more work-groups than the batch has work items; 1: a replay of a
+       captured graph with a fixed persistent grid */
+    int use_graph;
+    int reserved[3];
 } bmmc_server_options_t;
 
 typedef struct {

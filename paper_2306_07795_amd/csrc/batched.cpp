@@ -343,8 +343,13 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     hipEventRecord(bs->staged, stream);
 
     const int iters = batched_iters(o.iters);
-    const uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups
-                                           : (uint32_t)(ds->cu_count * batched_occupancy(iters));
+    uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(iters));
+    if (o.use_graph < 0) {
+        // plain launches: no more work-groups than the larger phase has items
+        const uint32_t* range = (const uint32_t*)h;
+        const uint32_t most = std::max(range[1] - range[0], range[2] - range[1]);
+        grid = std::max(1u, std::min(grid, most));
+    }
     const int hints = resolve_batch_hints(o, moved);
     if (o.use_graph >= 0) {
         st = build_graph(bs, grid, hints, iters);

@@ -298,6 +298,7 @@ void Server::dispatch_loop() {
                 bmmc_batch_options_t bo;
                 std::memset(&bo, 0, sizeof(bo));
                 bo.method = opt.method;
+                bo.use_graph = opt.use_graph > 0 ? 1 : -1;
                 int st;
                 {
                     std::lock_guard<std::mutex> dl(ds->mu);

@@ -153,11 +153,12 @@ def test_autotune_batched_small():
 
 # ------------------------------------------------------------------ server
 
+@pytest.mark.parametrize("use_graph", [0, 1])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
-def test_server_mix_equals_alone_equals_oracle(method):
+def test_server_mix_equals_alone_equals_oracle(method, use_graph):
     reqs = gen.poisson_requests(60, 20000.0, 7, n_lo=8, n_hi=20)
     pool = {}
-    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True, method=method)
+    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True, method=method, use_graph=use_graph)
     try:
         t0 = B.bmmc_server_now_ns() + 2_000_000
         tickets = []
