@@ -413,7 +413,8 @@ typedef struct {
    and one dispatcher thread.
    Requests are admitted in arrival order while input + output + scratch of
    all admitted, unfinished requests fits budget_bytes; every admitted request
-   joins the next batched launch on a free stream.
+   joins the next launch on a free stream (up to four requests as their own
+   tiled launches, more as one batched persistent launch).
    Errors: _ARG, _NOMEM. */
 int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out);
 

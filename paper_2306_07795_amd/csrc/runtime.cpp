@@ -205,7 +205,7 @@ static void kernel_name(char* buf, size_t len, const Plan& p, int hints) {
 }
 
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
-                 uint32_t grid, int hints, int order) {
+                 uint32_t grid, int hints, int order, void* scratch) {
     const size_t bytes = ((size_t)1 << plan.n) * (size_t)plan.w;
     hipError_t e;
     if (plan.npass == 0) {
@@ -227,8 +227,8 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
     if (!tiled_kernel_available(plan.w, ks.nt, ks.iters, hints))
         return set_error(BMMC_ERR_RANGE, "no tiled kernel for w=%d threads=%d iters=%d hints=%d", plan.w, ks.nt,
                          ks.iters, hints);
-    void* mid = nullptr;
-    if (plan.npass == 2) {
+    void* mid = scratch;
+    if (plan.npass == 2 && !mid) {
         int st = get_scratch(ds, stream, bytes, &mid);
         if (st != BMMC_OK) return st;
     }

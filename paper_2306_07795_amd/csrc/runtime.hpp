@@ -78,9 +78,10 @@ PlanOptions plan_options(const bmmc_options_t* o, int w);
 int resolve_hints(const bmmc_options_t* o, size_t bytes);
 int resolve_order(const bmmc_options_t* o);
 
-// Enqueue the passes of a plan (caller holds ds->mu).
+// Enqueue the passes of a plan (caller holds ds->mu).  Two-pass plans use
+// `scratch` when given (2^n * w bytes), else the per-stream scratch.
 int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, hipStream_t stream,
-                 uint32_t grid, int hints = 0, int order = 0);
+                 uint32_t grid, int hints = 0, int order = 0, void* scratch = nullptr);
 
 int validate_buffers(const void* in, const void* out, size_t bytes);
 

@@ -7,9 +7,10 @@
 //  * planner threads plan requests as they arrive;
 //  * the dispatcher admits planned requests in arrival order while their
 //    footprint (input + output + scratch) fits the budget, and whenever one
-//    of its K streams is free it launches every admitted request as one
-//    batched persistent launch on that stream, so launches overlap on the
-//    device and requests that arrive while others run join the next launch;
+//    of its K streams is free it launches every admitted request on that
+//    stream -- a few of them as their own tiled launches, more as one
+//    batched persistent launch -- so launches overlap on the device and
+//    requests that arrive while others run join the next launch;
 //  * completions are seen by polling each stream's event; latency is
 //    completion minus arrival.
 // Outputs and scratch come from one device arena of `budget` bytes managed as
@@ -88,6 +89,9 @@ class Buddy {
 };
 
 enum ReqState { kPending = 0, kPlanned, kAdmitted, kRunning, kDone, kFailed };
+
+// Launches of at most this many requests use the single-array kernels.
+constexpr int kDirectMax = 4;
 
 struct Request {
     int64_t ticket = 0;
@@ -299,10 +303,20 @@ void Server::dispatch_loop() {
                 std::memset(&bo, 0, sizeof(bo));
                 bo.method = opt.method;
                 bo.use_graph = opt.use_graph > 0 ? 1 : -1;
-                int st;
+                int st = BMMC_OK;
                 {
                     std::lock_guard<std::mutex> dl(ds->mu);
-                    st = enqueue_batched(ds, arrays, bo, s.stream);
+                    if (take <= (size_t)kDirectMax) {
+                        // a few arrays: their own tiled launches (tables in the
+                        // kernel arguments, no table upload, no persistent grid)
+                        for (size_t i = 0; i < take && st == BMMC_OK; i++) {
+                            const BatchArray& ba = arrays[i];
+                            st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, s.stream, 0,
+                                              resolve_hints(nullptr, ba.bytes), 0, ba.scratch);
+                        }
+                    } else {
+                        st = enqueue_batched(ds, arrays, bo, s.stream);
+                    }
                 }
                 if (st == BMMC_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = BMMC_ERR_HIP;
                 if (st != BMMC_OK) {
