@@ -282,3 +282,35 @@ def test_server_stats_reset_after_warm_up():
         assert B.bmmc_server_stats(srv)["completed"] == 1
     finally:
         B.bmmc_server_destroy(srv)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_server_burst_takes_the_batched_kernel(use_graph):
+    """Forty requests arriving at the same instant are admitted together and
+    run as batched launches (more than four per launch); every result equals
+    the oracle's."""
+    n_req = 40
+    srv = B.bmmc_server_create(1 << 30, streams=2, own_outputs=True, use_graph=use_graph)
+    try:
+        work = []
+        t0 = B.bmmc_server_now_ns() + 5_000_000
+        for k in range(n_req):
+            n, w = 10 + k % 9, (4, 8)[k % 2]
+            rows, c = gen.random_bmmc(n, 700 + k)
+            a = gen.data(n, w, 700 + k)
+            x = G.to_device(a)
+            work.append((n, w, rows, c, a, x))
+        torch.cuda.synchronize()
+        tickets = [B.bmmc_server_submit(srv, x, 0, n, rows, c, w, t0) for n, w, rows, c, a, x in work]
+        B.bmmc_server_drain(srv)
+        st = B.bmmc_server_stats(srv)
+        assert st["completed"] == n_req and st["mean_batch"] > 4
+        for tk, (n, w, rows, c, a, x) in zip(tickets, work):
+            done, out = B.bmmc_server_poll(srv, tk)
+            y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+            B.bmmc_copy(out, y, a.nbytes, G.stream())
+            G.sync()
+            assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
+            B.bmmc_server_release(srv, tk)
+    finally:
+        B.bmmc_server_destroy(srv)
