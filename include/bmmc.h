@@ -390,7 +390,10 @@ typedef struct {
        no more work-groups than the batch has work items; 1: a replay of a
        captured graph with a fixed persistent grid */
     int use_graph;
-    int reserved[3];
+    /* launches of at most this many requests run them as their own tiled
+       launches (0: default 4; negative: never, every launch is batched) */
+    int direct_max;
+    int reserved[2];
 } bmmc_server_options_t;
 
 typedef struct {
@@ -413,8 +416,8 @@ typedef struct {
    and one dispatcher thread.
    Requests are admitted in arrival order while input + output + scratch of
    all admitted, unfinished requests fits budget_bytes; every admitted request
-   joins the next launch on a free stream (up to four requests as their own
-   tiled launches, more as one batched persistent launch).
+   joins the next launch on a free stream (up to direct_max requests as their
+   own tiled launches, more as one batched persistent launch).
    Errors: _ARG, _NOMEM. */
 int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out);
 

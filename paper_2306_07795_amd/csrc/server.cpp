@@ -90,9 +90,6 @@ class Buddy {
 
 enum ReqState { kPending = 0, kPlanned, kAdmitted, kRunning, kDone, kFailed };
 
-// Launches of at most this many requests use the single-array kernels.
-constexpr int kDirectMax = 4;
-
 struct Request {
     int64_t ticket = 0;
     bmmc_desc_t desc{};
@@ -306,7 +303,8 @@ void Server::dispatch_loop() {
                 int st = BMMC_OK;
                 {
                     std::lock_guard<std::mutex> dl(ds->mu);
-                    if (take <= (size_t)kDirectMax) {
+                    const int direct_max = opt.direct_max == 0 ? 4 : opt.direct_max;
+                    if ((int64_t)take <= (int64_t)direct_max) {
                         // a few arrays: their own tiled launches (tables in the
                         // kernel arguments, no table upload, no persistent grid)
                         for (size_t i = 0; i < take && st == BMMC_OK; i++) {
