@@ -98,7 +98,7 @@ def cpu_baseline(a, n, rows, c, budget_s=12.0):
     while True:
         orc.permute(a, n, rows, c, 0)
         reps += 1
-        if time.perf_counter() - t0 > budget_s or reps >= 20:
+        if time.perf_counter() - t0 > budget_s or reps >= 200:
             break
     dt = (time.perf_counter() - t0) / reps
     # and once on a single thread
