@@ -31,9 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "BMMC permute GB/s (rd+wr) as % of device copy & HBM peak; batched p99 latency"
-# Autotuner results for this GPU model (JSON lines of the library's tuning
-# cache): loaded unless --retune, written by --save-tune.
-TUNE_DB = os.path.join(ROOT, "paper_2306_07795_amd", "tuning", "mi355x.jsonl")
+# Autotuner results for this GPU (JSON lines of the library's tuning cache,
+# which the library also loads by itself): used unless --retune; --save-tune
+# writes a run's results in the same form.
+TUNE_DB = os.path.join(ROOT, "paper_2306_07795_amd", "tuning", "gfx950.jsonl")
 HBM_PEAK_GBPS = 8000.0
 
 WORKLOADS = {

@@ -369,9 +369,11 @@ int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* stream, int
    given none.  Host only.  Errors: _ARG. */
 int bmmc_tune_lookup_batched(const bmmc_desc_t* descs, int count, bmmc_batch_options_t* opts_out);
 
-/* Save / load the tuning cache as JSON lines.  BMMC_TUNE_CACHE, when set,
-   names a file loaded on first use and rewritten after each tuning run.
-   bmmc_tune_load returns the number of entries read. */
+/* Save / load the tuning cache as JSON lines.  On first use the cache holds
+   the tuning results shipped with the library (tuning/gfx950.jsonl beside
+   libbmmc.so, measured on MI355X); BMMC_TUNE_CACHE, when set, names another
+   file to load instead (and to rewrite after each tuning run), an empty value
+   none.  bmmc_tune_load adds a file's entries and returns their number. */
 int bmmc_tune_save(const char* path);
 int bmmc_tune_load(const char* path);
 

@@ -5,11 +5,14 @@
 // batch signature for batched launches.  The cache can be saved to and loaded
 // from a JSON-lines file; BMMC_TUNE_CACHE names a file loaded on first use.
 #include <algorithm>
+#include <dlfcn.h>
+
 #include <cinttypes>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -69,11 +72,27 @@ int load_file(TuneCache& c, const char* path) {
     return count;
 }
 
+// The tuning results shipped with the library: tuning/gfx950.jsonl beside
+// libbmmc.so (found through the address of this function).
+std::string packaged_tuning_file() {
+    Dl_info info;
+    if (!dladdr((void*)&packaged_tuning_file, &info) || !info.dli_fname) return std::string();
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.find_last_of('/');
+    const std::string dir = slash == std::string::npos ? std::string(".") : lib.substr(0, slash);
+    return dir + "/tuning/gfx950.jsonl";
+}
+
 void ensure_loaded(TuneCache& c) {
     if (c.loaded) return;
     c.loaded = true;
     const char* path = std::getenv("BMMC_TUNE_CACHE");
-    if (path && *path) load_file(c, path);
+    if (path) {
+        if (*path) load_file(c, path);
+        return;  // an empty value asks for no tuning results at all
+    }
+    const std::string own = packaged_tuning_file();
+    if (!own.empty()) load_file(c, own.c_str());
 }
 
 int save_file(TuneCache& c, const char* path) {

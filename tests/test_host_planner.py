@@ -389,3 +389,19 @@ def test_tune_cache_classes_round_trip(tmp_path):
     B.bmmc_tune_save(str(out))
     saved = [l for l in out.read_text().splitlines() if '"n": 31, "w": 2' in l]
     assert len(saved) == 2 and '"class": 1, "used": 1' in saved[1]
+
+
+@pytest.mark.skipif("BMMC_TUNE_CACHE" in os.environ, reason="another tuning file is named")
+def test_packaged_tuning_results_are_loaded():
+    """The library starts from its shipped gfx950 tuning results: the default
+    workload's sizes have options for both matrix classes."""
+    import json
+    path = os.path.join(os.path.dirname(B.LIB_PATH), "tuning", "gfx950.jsonl")
+    entries = [json.loads(l) for l in open(path) if l.strip()]
+    assert any(e["kind"] == "plain" and e["n"] == 26 and e["w"] == 4 for e in entries)
+    rnd = B.bmmc_tune_lookup(26, 4, gen.random_bmmc(26, 0)[0])
+    bpc = B.bmmc_tune_lookup(26, 4, gen.bit_reversal_rows(26))
+    assert rnd is not None and bpc is not None
+    want = [e for e in entries if e["kind"] == "plain" and (e["n"], e["w"], e["method"], e["class"]) == (26, 4, 0, 0)][0]
+    assert (rnd["threads"], rnd["iters"], rnd["run_in"], rnd["run_out"]) == \
+        (want["threads"], want["iters"], want["run_in"], want["run_out"])
