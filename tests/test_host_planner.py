@@ -405,3 +405,35 @@ def test_packaged_tuning_results_are_loaded():
     want = [e for e in entries if e["kind"] == "plain" and (e["n"], e["w"], e["method"], e["class"]) == (26, 4, 0, 0)][0]
     assert (rnd["threads"], rnd["iters"], rnd["run_in"], rnd["run_out"]) == \
         (want["threads"], want["iters"], want["run_in"], want["run_out"])
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/bmmc.h compiles as C99 (no C++ or HIP types in the boundary) and
+    a C program that calls host-only entry points links against the library."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "bmmc.h"
+int main(void) {
+    uint64_t rows[4] = {8, 4, 2, 1};  /* bit reversal of 4 bits */
+    bmmc_plan_t plan;
+    if (bmmc_factorize(rows, 0, 4, &plan) != BMMC_OK) return 1;
+    if (plan.nfactors != 1) return 2;
+    uint64_t rows2[2] = {3, 3};
+    if (bmmc_invert(rows2, 0, 2, rows2, &rows2[0]) != BMMC_ERR_SINGULAR) return 3;
+    printf("%s\n", bmmc_strerror(BMMC_ERR_SINGULAR));
+    return 0;
+}
+''')
+    exe = tmp_path / "use"
+    libdir = os.path.dirname(B.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe),
+                        "-L", libdir, "-lbmmc", "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and "singular" in r.stdout
