@@ -77,24 +77,37 @@ typedef enum {
     BMMC_METHOD_NAIVE = 3
 } bmmc_method;
 
-/* Tuning knobs of one call; zero means "library default" everywhere. */
+/* Tuning knobs of one call; zero means "library default" everywhere.  Under
+   BMMC_METHOD_AUTO and _ONEPASS the defaults for 4- and 8-byte arrays of
+   more than 8 MiB depend on the size (up to 32 MiB, up to 256 MiB, beyond):
+   a tile shape and runs when none of threads, iters, t, run_in, run_out is
+   given, hints, tile_order and grid. */
 typedef struct {
     int method;    /* bmmc_method */
     int t;         /* run bits: reads and writes move runs of 2^t elements */
     int threads;   /* work-group size: 256, 512 or 1024 */
     int iters;     /* 16-byte vectors per thread per tile */
     int swizzle;   /* 1 (default) conflict-avoiding LDS layout, -1 plain layout */
-    int grid;      /* work-groups per pass launch; 0 = one per tile */
+    /* work-groups per pass launch; -1 = one per tile; 0 = library default:
+       one per tile, or for 4- and 8-byte arrays of more than 32 and up to
+       256 MiB under BMMC_METHOD_AUTO / _ONEPASS twice the work-groups
+       resident at once */
+    int grid;
     int run_in;    /* read-run bits (input runs of 2^run_in elements); 0 = t */
     int run_out;   /* write-run bits (output runs of 2^run_out elements); 0 = t */
     /* 1: non-temporal loads, 2: non-temporal stores, 3: both, 4: neither;
-       0: both for arrays of 64 MiB and more, neither below. */
+       0: library default (size-dependent as above, else both for arrays of
+       64 MiB and more, neither below). */
     int hints;
     /* 1: give each XCD a contiguous range of tiles (work-groups are dealt
        to the XCDs round-robin); 2: select tiles through XOR-combined index
-       bits; 3: both; 4: neither; 0: 2 for one-pass plans of tiled matrices
-       larger than a tile, 4 otherwise.  Adding 8 also fills the tile with
-       XOR-combined iteration bits instead of the lowest free index bits. */
+       bits; 3: both; 4: neither; 0: library default (size-dependent as
+       above, else 2 for one-pass plans of tiled matrices larger than a
+       tile, 4 otherwise).  Adding 8 also fills the tile with
+       XOR-combined iteration bits instead of the lowest free index bits.
+       Adding 16*k (k = 1..15) makes the k lowest tile-index bits step the
+       output by one write run each (k = 15: every tile-index bit that can),
+       so that tiles running side by side write neighbouring runs. */
     int tile_order;
     int reserved[2];
 } bmmc_options_t;

@@ -182,7 +182,8 @@ extern "C" int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_
                             int elem_bytes, const bmmc_options_t* opts, bmmc_emu_stats_t* stats) {
     if (!in || !out) return set_error(BMMC_ERR_ARG, "in/out must not be NULL");
     if (n < 0 || n > 30) return set_error(BMMC_ERR_RANGE, "emulation supports n <= 30");
-    PlanOptions po = plan_options(opts, elem_bytes);
+    const bmmc_options_t eff = effective_options(nullptr, n, elem_bytes, opts);
+    PlanOptions po = plan_options(&eff, elem_bytes);
     Plan p;
     int st = make_plan(A_rows, c, n, elem_bytes, po, &p);
     if (st != BMMC_OK) return set_error(st, "planning failed: %s", bmmc_strerror(st));

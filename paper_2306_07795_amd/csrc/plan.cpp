@@ -363,9 +363,25 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
     // XOR-ed with a random choice of the higher ones -- an invertible change
     // of basis of the same complement, which changes which tiles run
     // together but not what any tile holds.
+    // With out_adj = k > 0 (tb_mix >> 4), the first k tile-selecting vectors
+    // are instead the inputs T^-1 e_j of output bits j = b, b+1, ... reduced
+    // modulo the tile, so tiles of neighbouring index write neighbouring runs
+    // of the output (k = 15: as many as there are).
+    const int out_adj = (tb_mix >> 4) & 15;
     uint64_t tbv[kMaxBits];
     for (int i = 0; i < ntb; i++) tbv[i] = 1ull << tbpos[i];
-    if (tb_mix) {
+    if (out_adj) {
+        Basis cb = vb;
+        int nt = 0;
+        const int want = out_adj == 15 ? ntb : (out_adj < ntb ? out_adj : ntb);
+        for (int j = b; j < n && nt < want; j++) {
+            const uint64_t u = vb.reduce(Ti.col(j));
+            if (u && cb.insert(u)) tbv[nt++] = u;
+        }
+        for (int i = 0; i < ntb && nt < ntb; i++)
+            if (cb.insert(1ull << tbpos[i])) tbv[nt++] = 1ull << tbpos[i];
+        if (nt != ntb) return BMMC_ERR_INTERNAL;
+    } else if (tb_mix & 1) {
         uint64_t s = seed ^ 0x7B1Dull;
         for (int i = 0; i < ntb; i++) {
             s = mix64(s);
@@ -441,7 +457,7 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
         int ga = a, gb = b;
         if (opt.t <= 0 && opt.a <= 0 && opt.b <= 0) general_runs(gs, &ga, &gb);
         if (ga < gs.lv() || gb < gs.lv() || ga > gs.D() || gb > gs.D()) return BMMC_ERR_RANGE;
-        st = build_pass(A, c, ga, gb, gs, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0,
+        st = build_pass(A, c, ga, gb, gs, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? opt.tb_mix : 0,
                         opt.iter_mix);
         if (st != BMMC_OK) return st;
         p->npass = 1;
@@ -449,9 +465,9 @@ int make_plan(const uint64_t* rows, uint64_t c, int n, int w, const PlanOptions&
     }
     BitMat T1, T2;
     if (!factorize_ulp(A, nullptr, nullptr, nullptr, &T1, &T2)) return BMMC_ERR_SINGULAR;
-    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? 1 : 0, opt.iter_mix);
+    st = build_pass(T2, 0, a, b, ks, opt.swizzle, seed, &p->pass[0], opt.tb_mix > 0 ? opt.tb_mix : 0, opt.iter_mix);
     if (st != BMMC_OK) return st;
-    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix > 0 ? 1 : 0, opt.iter_mix);
+    st = build_pass(T1, c, a, b, ks, opt.swizzle, seed + 1, &p->pass[1], opt.tb_mix > 0 ? opt.tb_mix : 0, opt.iter_mix);
     if (st != BMMC_OK) return st;
     p->npass = 2;
     return BMMC_OK;

@@ -51,7 +51,10 @@ struct PlanOptions {
     int a = 0;        // read-run bits; 0 = t
     int b = 0;        // write-run bits; 0 = t
     int swizzle = 1;  // 0: plain layout, 1: conflict-avoiding XOR layout
-    int tb_mix = -1;  // 1: tile-selecting vectors are XOR combinations of index bits; -1: auto
+    // bit 0: tile-selecting vectors are XOR combinations of index bits;
+    // bits 4-7: how many of them step the output (neighbouring tiles write
+    // neighbouring runs; 15 = all); -1: auto
+    int tb_mix = -1;
     int iter_mix = 0; // 1: iteration vectors are XOR combinations of index bits
     bool shape_given = false;  // false: the default shape for the width and kind of tile
     KernelShape shape;         // used when shape_given

@@ -45,7 +45,7 @@ size_t PlanKeyHash::operator()(const PlanKey& k) const {
     mixin((uint64_t)k.n | ((uint64_t)k.w << 8) | ((uint64_t)k.method << 16) | ((uint64_t)k.t << 24) |
           ((uint64_t)k.nt << 32) | ((uint64_t)k.iters << 48) | ((uint64_t)k.swizzle << 60) |
           ((uint64_t)(k.tb_mix & 1) << 62) | ((uint64_t)k.iter_mix << 63));
-    mixin(k.c ^ ((uint64_t)k.a << 56) ^ ((uint64_t)k.b << 48));
+    mixin(k.c ^ ((uint64_t)k.a << 56) ^ ((uint64_t)k.b << 48) ^ ((uint64_t)(k.tb_mix >> 4) << 40));
     for (int i = 0; i < k.n; i++) mixin(k.rows[i]);
     return (size_t)h;
 }
@@ -163,6 +163,67 @@ LaunchScope::~LaunchScope() {
     if (stop) hipEventRecord(stop, stream);
 }
 
+// Library defaults of the general one-pass tile (BMMC_METHOD_AUTO and
+// _ONEPASS) for 4- and 8-byte arrays larger than 8 MiB, by size: measured
+// on gfx950 over random matrices and bit permutations of 2^21..2^28
+// elements.  Up to 256 MiB an array fits the last-level cache, where
+// non-temporal stores with cached loads and, from 32 MiB, a persistent grid
+// of twice the resident work-groups are best; beyond it both sides stream
+// through HBM with non-temporal loads and stores.  The tiles are ordered so
+// that neighbouring tiles write neighbouring runs.
+namespace {
+struct SizeDefault {
+    int w;
+    size_t lo, hi;  // lo < bytes <= hi
+    int nt, iters, a, b, hints, order;
+    bool persistent;
+};
+const SizeDefault kSizeDefaults[] = {
+    {4, (size_t)8 << 20, (size_t)32 << 20, 256, 8, 5, 8, 2, 4 + 16 * 6, false},
+    {4, (size_t)32 << 20, (size_t)256 << 20, 512, 8, 6, 7, 2, 4 + 16 * 15, true},
+    {4, (size_t)256 << 20, ~(size_t)0, 1024, 4, 6, 8, 3, 4 + 16 * 7, false},
+    {8, (size_t)8 << 20, (size_t)32 << 20, 256, 8, 7, 5, 2, 4 + 16 * 15, false},
+    {8, (size_t)32 << 20, (size_t)256 << 20, 1024, 4, 5, 7, 2, 1 + 16 * 8, true},
+    {8, (size_t)256 << 20, ~(size_t)0, 1024, 4, 5, 7, 3, 4 + 16 * 6, false},
+};
+}  // namespace
+
+bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc_options_t* o) {
+    bmmc_options_t e;
+    if (o)
+        e = *o;
+    else
+        std::memset(&e, 0, sizeof(e));
+    if (e.method != BMMC_METHOD_AUTO && e.method != BMMC_METHOD_ONEPASS) return e;
+    const size_t bytes = ((size_t)1 << n) * (size_t)w;
+    const SizeDefault* d = nullptr;
+    for (const SizeDefault& s : kSizeDefaults)
+        if (s.w == w && bytes > s.lo && bytes <= s.hi) {
+            d = &s;
+            break;
+        }
+    if (!d) return e;
+    // the runs and the tile shape go together: only when none is given
+    const bool shape_free = !e.threads && !e.iters && !e.t && !e.run_in && !e.run_out;
+    if (shape_free) {
+        e.threads = d->nt;
+        e.iters = d->iters;
+        e.run_in = d->a;
+        e.run_out = d->b;
+        e.t = d->a < d->b ? d->a : d->b;
+    }
+    if (!e.hints) e.hints = d->hints;
+    if (!e.tile_order) e.tile_order = d->order;
+    if (!e.grid && d->persistent && ds && ds->cu_count > 0) {
+        KernelShape ks = default_shape(w);
+        ks.nt = e.threads ? e.threads : ks.nt;
+        ks.iters = e.iters ? e.iters : ks.iters;
+        const int occ = tiled_occupancy(w, ks.nt, ks.iters, 0);
+        if (occ > 0) e.grid = 2 * ds->cu_count * occ;
+    }
+    return e;
+}
+
 PlanOptions plan_options(const bmmc_options_t* o, int w) {
     PlanOptions p;
     p.shape = default_shape(w);
@@ -172,7 +233,8 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     if (o->run_in) p.a = o->run_in;
     if (o->run_out) p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
-    if (o->tile_order) p.tb_mix = (o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1);
+    if (o->tile_order)
+        p.tb_mix = ((o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1)) | (((o->tile_order >> 4) & 15) << 4);
     p.iter_mix = (o->tile_order >> 3) & 1;
     if (o->threads > 0 || o->iters > 0) {
         // a shape given in part takes the rest from the default of its kind
@@ -338,7 +400,9 @@ int bmmc_plan_ex(const uint64_t* A_rows, uint64_t c, int n, int elem_bytes, cons
     if (!plan_out) return set_error(BMMC_ERR_ARG, "plan_out is NULL");
     if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
         return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
-    PlanOptions o = plan_options(opts, elem_bytes);
+    if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
+    const bmmc_options_t eff = effective_options(nullptr, n, elem_bytes, opts);
+    PlanOptions o = plan_options(&eff, elem_bytes);
     Plan p;
     int st = make_plan(A_rows, c, n, elem_bytes, o, &p);
     if (st != BMMC_OK) return set_error(st, "planning failed: %s", bmmc_strerror(st));
@@ -384,6 +448,8 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     if (!ds) return st;
     bmmc_options_t tuned;
     if (!opts && tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned)) opts = &tuned;
+    const bmmc_options_t eff = effective_options(ds, n, elem_bytes, opts);
+    opts = &eff;
     PlanOptions po = plan_options(opts, elem_bytes);
     std::shared_ptr<const Plan> plan;
     st = get_plan(ds, A_rows, c, n, elem_bytes, po, &plan);

@@ -74,6 +74,10 @@ struct LaunchScope {
 
 // Plan options from the public option struct.
 PlanOptions plan_options(const bmmc_options_t* o, int w);
+// The options a call runs with: o (NULL = all default) with the library's
+// size-dependent defaults of the general one-pass tile filled in where o
+// leaves them zero (the persistent grid only when ds is given).
+bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc_options_t* o);
 // Launch-time choices from the public option struct (zero = default).
 int resolve_hints(const bmmc_options_t* o, size_t bytes);
 int resolve_order(const bmmc_options_t* o);

@@ -257,20 +257,40 @@ double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, 
     return total;
 }
 
-// Times every candidate on the matrices (`reps` runs each), then the fastest
-// few again with four times the runs, so that noise does not pick the winner;
-// the fastest options and their time per matrix.
+// Two stages, each candidate timed on the matrices (`reps` runs each): first
+// tile shape, read/write runs, cache hints and method under two tile orders
+// and both grid kinds; then, for the six fastest of those, every tile order
+// and grid kind.  The library default for the size is always a candidate.
+// Returns the fastest options and their time per matrix.
 void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with_tiled,
                    const std::vector<TuneMatrix>& mats, const void* in, void* out, hipStream_t stream, int reps,
                    bmmc_options_t* bo, double* best) {
     static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}, {1024, 4}, {256, 16}};
+    // tile orders: plain, and neighbouring tiles writing neighbouring runs
+    // for the 7 lowest tile-index bits (best for most large arrays)
+    static const int kStage1Orders[] = {4, 4 + 16 * 7};
+    static const int kOutAdj[] = {0, 2, 4, 5, 6, 7, 8, 9, 10, 12, 15};
+    const size_t kBases = 6, kFinal = 8;
     std::vector<std::pair<double, bmmc_options_t>> timed;
     Timer tm;
     const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
     // non-temporal stores (2) or loads and stores (3) beyond the last-level
     // cache, none (4) or stores only below it
     const int hint_set[2][2] = {{4, 2}, {2, 3}};
-    const int* hints_of = hint_set[bytes >= ((size_t)64 << 20) ? 1 : 0];
+    const int* hints_of = hint_set[bytes > ((size_t)8 << 20) ? 1 : 0];
+    auto persistent_grid = [&](const bmmc_options_t& o) {
+        return ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
+    };
+    auto run = [&](const bmmc_options_t& o) {
+        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, reps, tm);
+        if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
+    };
+    {
+        bmmc_options_t o;
+        std::memset(&o, 0, sizeof(o));
+        o.method = method;
+        run(effective_options(ds, n, elem_bytes, &o));
+    }
     // runs of at least one 128-byte line on both sides
     int min_run = 7;
     for (int w = elem_bytes; w > 1; w >>= 1) min_run--;
@@ -280,7 +300,6 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
         ks.nt = sh[0];
         ks.iters = sh[1];
         const int D = ks.D();
-        const int occ = tiled_occupancy(elem_bytes, ks.nt, ks.iters, 0);
         const int lo = min_run > ks.lv() ? min_run : ks.lv();
         // (read-run, write-run) bits filling the tile, or all but one bit of it
         for (int sum = D; sum >= D - 1; sum--) {
@@ -288,7 +307,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
                 const int b = sum - a;
                 for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
                     for (int hi = 0; hi < 2; hi++) {
-                        for (int order : {4, 2, 10, 3, 11}) {
+                        for (int order : kStage1Orders) {
                             for (int g = 0; g < 2; g++) {
                                 bmmc_options_t o;
                                 std::memset(&o, 0, sizeof(o));
@@ -302,9 +321,8 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
                                 o.swizzle = 1;
                                 o.hints = hints_of[hi];
                                 o.tile_order = order;
-                                o.grid = g == 0 ? 0 : ds->cu_count * occ * 2;
-                                const double t = time_options(n, elem_bytes, mats, o, in, out, stream, reps, tm);
-                                if (t > 0) timed.push_back({t, o});  // else: shape does not fit this size
+                                o.grid = g == 0 ? -1 : persistent_grid(o);
+                                run(o);
                             }
                         }
                     }
@@ -312,17 +330,49 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
             }
         }
     }
-    *best = 1e30;
-    std::memset(bo, 0, sizeof(*bo));
-    std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-    const size_t keep = timed.size() < 6 ? timed.size() : 6;
-    for (size_t i = 0; i < keep; i++) {
-        const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, reps * 4, tm);
-        if (t > 0 && t < *best) {
-            *best = t;
-            *bo = timed[i].second;
+    auto by_time = [](const auto& x, const auto& y) { return x.first < y.first; };
+    std::sort(timed.begin(), timed.end(), by_time);
+    // stage 2: tile orders and grid kinds of the fastest distinct settings
+    std::vector<bmmc_options_t> base;
+    for (const auto& tv : timed) {
+        bool seen = false;
+        for (const auto& b : base)
+            seen |= b.method == tv.second.method && b.threads == tv.second.threads && b.iters == tv.second.iters &&
+                    b.run_in == tv.second.run_in && b.run_out == tv.second.run_out && b.hints == tv.second.hints;
+        if (!seen) base.push_back(tv.second);
+        if (base.size() == kBases) break;
+    }
+    for (const bmmc_options_t& b : base) {
+        for (int k : kOutAdj) {
+            for (int order : {4, 1, 2, 3}) {
+                if (k && order >= 2) continue;  // XOR-mixed selection does not combine with k
+                for (int g = 0; g < 2; g++) {
+                    bmmc_options_t o = b;
+                    o.tile_order = order + 16 * k;
+                    o.grid = g == 0 ? -1 : persistent_grid(o);
+                    run(o);
+                }
+            }
         }
     }
+    *best = 1e30;
+    std::memset(bo, 0, sizeof(*bo));
+    std::sort(timed.begin(), timed.end(), by_time);
+    // the fastest few again, in two interleaved rounds of twice the runs
+    // (the better of each candidate's two), so that drift and noise do not
+    // pick the winner
+    const size_t keep = timed.size() < kFinal ? timed.size() : kFinal;
+    std::vector<double> again(keep, 1e30);
+    for (int round = 0; round < 2; round++)
+        for (size_t i = 0; i < keep; i++) {
+            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, reps * 2, tm);
+            if (t > 0 && t < again[i]) again[i] = t;
+        }
+    for (size_t i = 0; i < keep; i++)
+        if (again[i] < *best) {
+            *best = again[i];
+            *bo = timed[i].second;
+        }
     if (*best < 1e30) *best /= (double)mats.size();
 }
 

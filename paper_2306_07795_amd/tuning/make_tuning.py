@@ -1,0 +1,51 @@
+"""Regenerate a tuning file with the library's own autotuner.
+
+Runs bmmc_autotune for every array size of 4- and 8-byte elements from one
+tile to 1 GiB, for the default method (random matrices and bit permutations,
+stored as two classes) and for the two-pass scheme of Section 5.2 at the
+larger sizes, then writes the tuning cache as JSON lines.  The library loads
+`gfx950.jsonl` beside this script on first use; the batched entry for a given
+batch comes from `bench.py --retune --save-tune PATH`.
+
+    BMMC_TUNE_CACHE= python paper_2306_07795_amd/tuning/make_tuning.py --out PATH
+"""
+import argparse
+import os
+import sys
+import time
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))))
+
+from paper_2306_07795_amd import binding as B  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", required=True, help="tuning file to write (JSON lines)")
+    ap.add_argument("--widths", default="4,8", help="element widths in bytes")
+    ap.add_argument("--max-bytes-log2", type=int, default=30, help="largest array: 2^this bytes")
+    ap.add_argument("--min-n", type=int, default=12, help="smallest n")
+    ap.add_argument("--tiled-from-log2", type=int, default=24,
+                    help="also tune the two-pass scheme from arrays of 2^this bytes")
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    if os.environ.get("BMMC_TUNE_CACHE", None) != "":
+        print("note: BMMC_TUNE_CACHE is not empty; the entries of that file are kept", flush=True)
+    for w in (int(v) for v in args.widths.split(",")):
+        lw = w.bit_length() - 1
+        for n in range(args.min_n, args.max_bytes_log2 - lw + 1):
+            methods = [B.METHOD_AUTO]
+            if n + lw >= args.tiled_from_log2:
+                methods.append(B.METHOD_TILED)
+            for m in methods:
+                t0 = time.time()
+                opts, ms = B.bmmc_autotune(n, w, m, None, args.reps)
+                gbps = 2.0 * (1 << n) * w / (ms * 1e-3) / 1e9
+                print(f"n={n} w={w} method={m}: {ms:.4f} ms ({gbps:.0f} GB/s) in {time.time() - t0:.1f} s  {opts}",
+                      flush=True)
+    B.bmmc_tune_save(args.out)
+    print("wrote", args.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -110,6 +110,8 @@ def test_onepass_method(n, w):
     {"threads": 256, "iters": 2}, {"threads": 1024, "iters": 4}, {"t": 5},
     {"swizzle": -1}, {"grid": 64}, {"grid": 1}, {"threads": 256, "iters": 16, "t": 7},
     {"run_in": 7, "run_out": 6, "threads": 512, "iters": 8, "tile_order": 2, "hints": 3},
+    {"tile_order": 4 + 16 * 15, "grid": -1}, {"tile_order": 1 + 16 * 6, "grid": 96},
+    {"threads": 1024, "iters": 4, "run_in": 6, "run_out": 8, "tile_order": 4 + 16 * 7, "hints": 3},
 ])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 def test_shapes_and_grids(opts, method):
@@ -160,6 +162,20 @@ def test_full_size_sweep_sampled(case):
     got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_TILED}) if case.endswith("tiled") \
         else run(n, rows, c, w, a)
     sampled_check(n, rows, c, w, got, a)
+
+
+@pytest.mark.parametrize("kind", ["random", "bitrev"])
+@pytest.mark.parametrize("n,w", [(22, 4), (23, 4), (24, 4), (21, 8), (22, 8), (23, 8), (27, 4), (26, 8)])
+def test_size_dependent_defaults(n, w, kind):
+    """The library's size-dependent defaults (explicit method, so no tuning
+    file entry applies): in full up to 64 MiB, on sampled outputs above."""
+    rows, c = gen.random_bmmc(n, 2 * n + w) if kind == "random" else (gen.bit_reversal_rows(n), 0)
+    a = gen.data(n, w, 3)
+    got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_AUTO})
+    if (1 << n) * w <= (64 << 20):
+        assert np.array_equal(got, O.permute(a, n, rows, c))
+    else:
+        sampled_check(n, rows, c, w, got, a)
 
 
 def test_copy_kernel():

@@ -325,6 +325,42 @@ def test_emulation_shapes(opts):
         assert st["lds_conflicts64"] == 0
 
 
+@pytest.mark.parametrize("order", [4 + 16, 1 + 16 * 6, 2 + 16 * 3, 4 + 16 * 15])
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+@pytest.mark.parametrize("name,mk", [c for c in CASES if c[0] in ("random", "bitrev", "swap", "bpc")],
+                         ids=["random", "bitrev", "swap", "bpc"])
+@pytest.mark.parametrize("w", [4, 8])
+def test_emulation_output_ordered_tiles(name, mk, w, method, order):
+    """Tiles selected so that neighbouring tiles write neighbouring runs: the
+    same permutation, every tile still reading and writing whole lines."""
+    n = 17
+    rows, c = mk(n, 3 * n + w)
+    st = emulate_check(n, rows, c, w, {"method": method, "tile_order": order})
+    assert st["read_lines"] == st["read_lines_min"]
+    assert st["write_lines"] == st["write_lines_min"]
+
+
+@pytest.mark.parametrize("n,w,a,d", [
+    (21, 4, 6, 13),   # 8 MiB: the general tile's own default
+    (22, 4, 5, 13),   # 16 MiB: 256 x 8 vectors, 2^5-element reads
+    (24, 4, 6, 14),   # 64 MiB: 512 x 8
+    (27, 4, 6, 14),   # 512 MiB: 1024 x 4
+    (20, 8, 7, 12),   # 8 MiB
+    (21, 8, 7, 12),   # 16 MiB: 256 x 8
+    (23, 8, 5, 13),   # 64 MiB: 1024 x 4
+    (26, 8, 5, 13),   # 512 MiB
+])
+def test_size_dependent_defaults(n, w, a, d):
+    rows, c = gen.random_bmmc(n, 11)
+    p = B.bmmc_plan_ex(rows, c, n, w, None)
+    assert p.nfactors == 1 and p.tile_bits[0] == d
+    assert bin(p.col_mask[0]).count("1") == a
+    # given runs keep the general tile's default shape (2^13 4-byte elements)
+    q = B.bmmc_plan_ex(rows, c, n, w, {"run_in": 7, "run_out": 5})
+    assert bin(q.col_mask[0]).count("1") == 7
+    assert q.tile_bits[0] == (13 if w == 4 else 12)
+
+
 def test_auto_takes_one_pass_and_tiled_the_papers_two():
     """Auto: one pass for every A (a tiled pass, or one general tile);
     the tiled method: the paper's factorization, two passes unless A is tiled."""
