@@ -296,8 +296,13 @@ int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint6
 
 /* ------------------------------------------------------- device calls */
 
-/* The permutation out[A.x XOR c] = in[x] (Section 2), by BMMC_METHOD_AUTO or
-   by the options bmmc_autotune stored for (n, elem_bytes).  Plans are cached
+/* The permutation out[A.x XOR c] = in[x] (Section 2), by BMMC_METHOD_AUTO
+   with the options bmmc_autotune stored for (n, elem_bytes) and the class of
+   A, else with the size-dependent defaults.  These are tuned for a call
+   repeated on the same buffers; where each call reads what the one before
+   it wrote, non-temporal loads with cached stores (hints 1, through
+   bmmc_permute_ex) are faster for arrays that fit the last-level cache.
+   Plans are cached
    by (A, c, n, elem_bytes, options); two-pass plans (BMMC_METHOD_TILED) use a
    scratch array of 2^n * elem_bytes owned by the library (kept per device
    and stream, grown on demand).
