@@ -343,7 +343,7 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     }
 
 
-def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0):
+def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0, solo_log2=0):
     """Open-loop Poisson arrivals at `rate` requests/s for `seconds`: n uniform
     in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs resident in
     a pool per (n, width); outputs and scratch from the server's HBM budget.
@@ -361,7 +361,8 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0
     for r in reqs:
         mats[r["id"]] = gen.random_bmmc(r["n"], r["seed"])
     torch.cuda.synchronize()
-    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2, use_graph=use_graph, direct_max=direct_max)
+    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2, use_graph=use_graph, direct_max=direct_max,
+                               solo_log2=solo_log2)
     try:
         # warm-up: a quarter second of the same stream (other matrices), then
         # the statistics start afresh
@@ -556,7 +557,7 @@ def main():
                     help="print the sorting-network table (compiled passes vs direct) and exit")
     ap.add_argument("--served-sweep", action="store_true",
                     help="print the served form at 5k, 10k, 15k and 20k requests/s (and at 20k "
-                         "with batched launches only) and exit")
+                         "with batched launches only, and without single-array plans) and exit")
     args = ap.parse_args()
     if args.transpose_sweep:
         print(json.dumps(transpose_sweep()), flush=True)
@@ -570,6 +571,8 @@ def main():
         rows += [dict(bench_served(20000.0, args.served_seconds, direct_max=-1, use_graph=g),
                       mode="batched launches only" + (", graph replay" if g else ""))
                  for g in (0, 1)]
+        rows += [dict(bench_served(20000.0, args.served_seconds, solo_log2=-1),
+                      mode="no request planned as a single-array call")]
         print(json.dumps({"workload": "served load sweep", "table": rows}), flush=True)
         return
     if args.traffic_from:

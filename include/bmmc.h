@@ -413,7 +413,12 @@ typedef struct {
     /* launches of at most this many requests run them as their own tiled
        launches (0: default 4; negative: never, every launch is batched) */
     int direct_max;
-    int reserved[2];
+    /* requests of at least 2^solo_log2 bytes are planned like a
+       bmmc_permute call without options (tuned options of their size and
+       matrix class) and always run as their own launch (0: default 24,
+       16 MiB; negative: never) */
+    int solo_log2;
+    int reserved[1];
 } bmmc_server_options_t;
 
 typedef struct {

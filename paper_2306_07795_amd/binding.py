@@ -83,7 +83,7 @@ class ServerStats(_c.Structure):
 class ServerOptions(_c.Structure):
     _fields_ = [("budget_bytes", _i64), ("streams", _i32), ("max_batch", _i32),
                 ("own_outputs", _i32), ("method", _i32), ("use_graph", _i32), ("direct_max", _i32),
-                ("reserved", _i32 * 2)]
+                ("solo_log2", _i32), ("reserved", _i32 * 1)]
 
 
 _lib = None
@@ -506,7 +506,7 @@ def bmmc_tune_load(path: str):
 
 def bmmc_server_create(budget_bytes: int, streams: int = 4, max_batch: int = 0,
                        own_outputs: int = 1, method: int = METHOD_AUTO, use_graph: int = 0,
-                       direct_max: int = 0):
+                       direct_max: int = 0, solo_log2: int = 0):
     """own_outputs: 0 caller passes out, 1 server allocates and keeps it until
     release, 2 server allocates and drops it at completion."""
     o = ServerOptions()
@@ -517,6 +517,7 @@ def bmmc_server_create(budget_bytes: int, streams: int = 4, max_batch: int = 0,
     o.method = method
     o.use_graph = int(use_graph)
     o.direct_max = int(direct_max)
+    o.solo_log2 = int(solo_log2)
     h = _vp()
     _check(lib().bmmc_server_create(_c.byref(o), _c.byref(h)))
     return h.value

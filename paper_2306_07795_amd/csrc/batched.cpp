@@ -300,6 +300,9 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iter
     // Arrays of one element, too small for 16-byte vectors, or of 1- or
     // 2-byte elements take the single-array kernels.
     out->single = out->plan->npass == 0 || out->plan->naive || d.elem_bytes < 4;
+    out->grid = 0;
+    out->hints = resolve_hints(nullptr, out->bytes);
+    out->order = 0;
     return BMMC_OK;
 }
 
@@ -309,7 +312,8 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     int st;
     for (size_t i = 0; i < arrays.size(); i++) {
         if (arrays[i].single) {
-            st = enqueue_plan(ds, *arrays[i].plan, arrays[i].in, arrays[i].out, stream, 0);
+            const BatchArray& a = arrays[i];
+            st = enqueue_plan(ds, *a.plan, a.in, a.out, stream, a.grid, a.hints, a.order, a.scratch);
             if (st != BMMC_OK) return st;
         } else if (arrays[i].plan->npass == 2 && !arrays[i].scratch) {
             return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");

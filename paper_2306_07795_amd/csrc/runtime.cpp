@@ -343,6 +343,25 @@ static void fill_public_plan(const Plan& p, bmmc_plan_t* out) {
     }
 }
 
+int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out) {
+    bmmc_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.method = method;
+    tuned_options(d.n, d.elem_bytes, method, matrix_class(d.A_rows, d.n), &o);  // else the defaults
+    const bmmc_options_t eff = effective_options(ds, d.n, d.elem_bytes, &o);
+    const int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, plan_options(&eff, d.elem_bytes), &out->plan);
+    if (st != BMMC_OK) return st;
+    out->in = d.in;
+    out->out = d.out;
+    out->scratch = nullptr;
+    out->bytes = ((size_t)1 << d.n) * (size_t)d.elem_bytes;
+    out->single = true;
+    out->grid = (uint32_t)eff.grid;
+    out->hints = resolve_hints(&eff, out->bytes);
+    out->order = resolve_order(&eff);
+    return BMMC_OK;
+}
+
 }  // namespace bmmc
 
 using namespace bmmc;
@@ -455,7 +474,7 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     st = get_plan(ds, A_rows, c, n, elem_bytes, po, &plan);
     if (st != BMMC_OK) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
-    return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, opts ? (uint32_t)opts->grid : 0,
+    return enqueue_plan(ds, *plan, in, out, (hipStream_t)stream, (uint32_t)opts->grid,
                         resolve_hints(opts, bytes), resolve_order(opts));
 }
 

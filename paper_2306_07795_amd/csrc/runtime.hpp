@@ -96,11 +96,18 @@ struct BatchArray {
     void* scratch = nullptr;  // 2^n * w bytes for two-pass plans
     size_t bytes = 0;
     bool single = false;      // runs through the single-array kernels
+    // launch settings of a single array (enqueue_plan's grid, hints, order)
+    uint32_t grid = 0;
+    int hints = 0, order = 0;
     std::shared_ptr<const Plan> plan;
 };
 
 int batch_validate(const bmmc_desc_t* descs, int count);
 int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out);
+// Plan one array as a single-array call without options would run it (the
+// tuned options of its size and matrix class, else the size defaults, for
+// `method`); marks it single, with those launch settings.
+int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchArray* out);
 // Enqueue one batched launch (caller holds ds->mu).
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream);

@@ -98,6 +98,9 @@ struct Request {
     int64_t planned_ns = 0, launched_ns = 0;
     int64_t done_ns = 0;
     std::shared_ptr<const Plan> plan;
+    bool solo = false;  // planned as a single-array call: always its own launch
+    uint32_t grid = 0;  // launch settings of its own launch
+    int hints = 0, order = 0;
     size_t bytes = 0;
     size_t footprint = 0;
     int64_t out_off = -1, scratch_off = -1;
@@ -128,6 +131,7 @@ struct Server {
     size_t arena_bytes = 0;
     Buddy buddy;
     int64_t in_use = 0, peak = 0;
+    size_t solo_bytes = 0;  // requests this large are planned as single-array calls (0: none)
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -201,7 +205,10 @@ void Server::plan_loop() {
         to_plan.pop_front();
         lk.unlock();
         BatchArray ba;
-        int st = plan_batch_array(ds, r->desc, opt.method, 0, &ba);
+        const size_t bytes = ((size_t)1 << r->desc.n) * (size_t)r->desc.elem_bytes;
+        const bool solo = solo_bytes > 0 && bytes >= solo_bytes && r->desc.elem_bytes >= 4;
+        int st = solo ? plan_single_array(ds, r->desc, opt.method, &ba)
+                      : plan_batch_array(ds, r->desc, opt.method, 0, &ba);
         lk.lock();
         if (st != BMMC_OK) {
             r->status = st;
@@ -212,6 +219,10 @@ void Server::plan_loop() {
             continue;
         }
         r->plan = ba.plan;
+        r->solo = solo;
+        r->grid = ba.grid;
+        r->hints = ba.hints;
+        r->order = ba.order;
         r->state = kPlanned;
         r->planned_ns = now_ns();
         // planners finish out of order: keep `ready` in arrival order
@@ -290,7 +301,10 @@ void Server::dispatch_loop() {
                     ba.scratch = r->scratch;
                     ba.bytes = r->bytes;
                     ba.plan = r->plan;
-                    ba.single = r->plan->npass == 0 || r->plan->naive || r->desc.elem_bytes < 4;
+                    ba.single = r->solo || r->plan->npass == 0 || r->plan->naive || r->desc.elem_bytes < 4;
+                    ba.grid = r->grid;
+                    ba.hints = r->hints;
+                    ba.order = r->order;
                     r->state = kRunning;
                     r->launched_ns = now_ns();
                     s.reqs.push_back(r);
@@ -309,8 +323,8 @@ void Server::dispatch_loop() {
                         // kernel arguments, no table upload, no persistent grid)
                         for (size_t i = 0; i < take && st == BMMC_OK; i++) {
                             const BatchArray& ba = arrays[i];
-                            st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, s.stream, 0,
-                                              resolve_hints(nullptr, ba.bytes), 0, ba.scratch);
+                            st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, s.stream, ba.grid, ba.hints,
+                                              ba.order, ba.scratch);
                         }
                     } else {
                         st = enqueue_batched(ds, arrays, bo, s.stream);
@@ -368,6 +382,8 @@ extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** hand
     s->opt = *opts;
     if (s->opt.streams <= 0) s->opt.streams = 4;
     if (s->opt.streams > 16) s->opt.streams = 16;
+    if (s->opt.solo_log2 > 40) return set_error(BMMC_ERR_ARG, "solo_log2 = %d above 40", s->opt.solo_log2);
+    s->solo_bytes = s->opt.solo_log2 < 0 ? 0 : (size_t)1 << (s->opt.solo_log2 == 0 ? 24 : s->opt.solo_log2);
     s->ds = ds;
     s->device = ds->device;
     // Arena: the largest power of two not above the budget, for outputs and scratch.

@@ -153,12 +153,16 @@ def test_autotune_batched_small():
 
 # ------------------------------------------------------------------ server
 
+@pytest.mark.parametrize("solo_log2", [0, 16, -1])
 @pytest.mark.parametrize("use_graph", [0, 1])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
-def test_server_mix_equals_alone_equals_oracle(method, use_graph):
+def test_server_mix_equals_alone_equals_oracle(method, use_graph, solo_log2):
+    """solo_log2 16: requests of 64 KiB and more are planned as single-array
+    calls (their own launches, tuned options) beside batched small ones."""
     reqs = gen.poisson_requests(60, 20000.0, 7, n_lo=8, n_hi=20)
     pool = {}
-    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True, method=method, use_graph=use_graph)
+    srv = B.bmmc_server_create(1 << 30, streams=3, own_outputs=True, method=method, use_graph=use_graph,
+                               solo_log2=solo_log2)
     try:
         t0 = B.bmmc_server_now_ns() + 2_000_000
         tickets = []
