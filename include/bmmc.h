@@ -149,7 +149,7 @@ typedef struct {
     int method;         /* bmmc_method for the arrays larger than a tile */
     int hints;          /* as bmmc_options_t.hints (0: non-temporal above 64 MiB moved) */
     int iters;          /* 16-byte vectors per thread per tile: 4 (default, 16 KiB tiles) or 8 */
-    int reserved[1];
+    int tile_order;     /* as bmmc_options_t.tile_order, bits 1, 2 and 16*k (0: plain order) */
 } bmmc_batch_options_t;
 
 /* Per-kernel timing gathered between bmmc_profile_begin and _end. */
@@ -375,9 +375,10 @@ int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
    defaults).  Host only.  Errors: _ARG, _RANGE. */
 int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows, bmmc_options_t* opts_out);
 
-/* Time chunk size, queue order and persistent grid size of the batched
-   kernel on this very batch (it runs the batch 1 + reps times per candidate);
-   the fastest is cached for batches with the same histogram of (n, width). */
+/* Time method, tile size, chunk size, queue order and persistent grid size
+   of the batched kernel on this very batch, then tile orders for the best
+   (it runs the batch 1 + reps times per candidate); the fastest is cached
+   for batches with the same histogram of (n, width). */
 int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* stream, int reps,
                           bmmc_batch_options_t* best_out, double* best_ms);
 

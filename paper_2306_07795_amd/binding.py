@@ -56,7 +56,7 @@ class Desc(_c.Structure):
 class BatchOptions(_c.Structure):
     _fields_ = [("workgroups", _i32), ("chunk_tiles", _i32), ("order", _i32),
                 ("use_graph", _i32), ("method", _i32), ("hints", _i32), ("iters", _i32),
-                ("reserved", _i32 * 1)]
+                ("tile_order", _i32)]
 
 
 class KernelStat(_c.Structure):

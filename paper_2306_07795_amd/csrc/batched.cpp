@@ -281,9 +281,11 @@ int batch_validate(const bmmc_desc_t* descs, int count) {
 }
 
 
-int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out) {
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out,
+                     int tile_order) {
     PlanOptions po;
     po.method = (method == BMMC_METHOD_ONEPASS || method == BMMC_METHOD_TILED) ? method : kMethodAuto;
+    po.tb_mix = tile_order_mix(tile_order);
     if (d.elem_bytes >= 4) {
         // the batched kernel's one shape
         po.shape = default_shape(d.elem_bytes);
@@ -401,6 +403,7 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     hipStream_t stream = (hipStream_t)stream_;
@@ -409,7 +412,7 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     size_t scratch_total = 0;
     std::vector<size_t> offs(count, 0);
     for (int i = 0; i < count; i++) {
-        st = plan_batch_array(ds, descs[i], o.method, o.iters, &arrays[i]);
+        st = plan_batch_array(ds, descs[i], o.method, o.iters, &arrays[i], o.tile_order);
         if (st != BMMC_OK) return set_error(st, "array %d: %s", i, bmmc_last_error());
         if (!arrays[i].single && arrays[i].plan->npass == 2) {
             offs[i] = scratch_total;
@@ -462,6 +465,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
@@ -472,7 +476,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     size_t scratch_total = 0;
     std::vector<size_t> offs(count, 0);
     for (int i = 0; i < count; i++) {
-        st = plan_batch_array(ds, descs[i], o.method, o.iters, &pb->arrays[i]);
+        st = plan_batch_array(ds, descs[i], o.method, o.iters, &pb->arrays[i], o.tile_order);
         if (st != BMMC_OK) {
             delete pb;
             return set_error(st, "array %d: %s", i, bmmc_last_error());

@@ -224,6 +224,11 @@ bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc
     return e;
 }
 
+int tile_order_mix(int t) {
+    if (!t) return -1;
+    return ((t & 4) ? 0 : ((t >> 1) & 1)) | (((t >> 4) & 15) << 4);
+}
+
 PlanOptions plan_options(const bmmc_options_t* o, int w) {
     PlanOptions p;
     p.shape = default_shape(w);
@@ -233,8 +238,7 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
     if (o->run_in) p.a = o->run_in;
     if (o->run_out) p.b = o->run_out;
     p.swizzle = o->swizzle < 0 ? 0 : 1;
-    if (o->tile_order)
-        p.tb_mix = ((o->tile_order & 4) ? 0 : ((o->tile_order >> 1) & 1)) | (((o->tile_order >> 4) & 15) << 4);
+    p.tb_mix = tile_order_mix(o->tile_order);
     p.iter_mix = (o->tile_order >> 3) & 1;
     if (o->threads > 0 || o->iters > 0) {
         // a shape given in part takes the rest from the default of its kind

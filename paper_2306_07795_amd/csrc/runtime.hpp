@@ -103,7 +103,10 @@ struct BatchArray {
 };
 
 int batch_validate(const bmmc_desc_t* descs, int count);
-int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out);
+int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iters, BatchArray* out,
+                     int tile_order = 0);
+// PlanOptions::tb_mix of a tile_order option (bits 1, 2 and 16*k; 0: -1, automatic)
+int tile_order_mix(int tile_order);
 // Plan one array as a single-array call without options would run it (the
 // tuned options of its size and matrix class, else the size defaults, for
 // `method`); marks it single, with those launch settings.

@@ -62,6 +62,11 @@ int load_file(TuneCache& c, const char* path) {
         uint64_t sig;
         if (std::sscanf(line,
                         "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
+                        "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"ms\": %lf}",
+                        &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &b.iters, &b.tile_order,
+                        &ms) == 8 ||
+            std::sscanf(line,
+                        "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
                         "\"order\": %d, \"method\": %d, \"iters\": %d, \"ms\": %lf}",
                         &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &b.iters, &ms) == 7) {
             c.batch[sig] = {b, ms};
@@ -113,8 +118,9 @@ int save_file(TuneCache& c, const char* path) {
         const bmmc_batch_options_t& b = kv.second.first;
         std::fprintf(f,
                      "{\"kind\": \"batch\", \"sig\": \"%016" PRIx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
-                     "\"order\": %d, \"method\": %d, \"iters\": %d, \"ms\": %.6f}\n",
-                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, b.iters, kv.second.second);
+                     "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"ms\": %.6f}\n",
+                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, b.iters, b.tile_order,
+                     kv.second.second);
     }
     std::fclose(f);
     return BMMC_OK;
@@ -455,6 +461,22 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     bmmc_batch_options_t bo;
     std::memset(&bo, 0, sizeof(bo));
     Timer tm;
+    // time graph replays of a resident batch: device time only
+    auto time_batch = [&](const bmmc_batch_options_t& o, double* per) -> int {
+        void* pb = nullptr;
+        int s2 = bmmc_batch_create(descs, count, &o, &pb);
+        if (s2 != BMMC_OK) return s2;
+        bmmc_batch_launch(pb, stream);  // warm-up
+        hipEventRecord(tm.a, stream);
+        for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
+        hipEventRecord(tm.b, stream);
+        hipEventSynchronize(tm.b);
+        bmmc_batch_destroy(pb);
+        float ms = 0;
+        hipEventElapsedTime(&ms, tm.a, tm.b);
+        *per = ms / reps;
+        return BMMC_OK;
+    };
     for (int method : {BMMC_METHOD_AUTO, BMMC_METHOD_TILED}) {
         for (int iters : {4, 8}) {
             const int occ = batched_occupancy(iters);
@@ -468,19 +490,9 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
                         o.chunk_tiles = chunk;
                         o.order = order;
                         o.workgroups = ds->cu_count * occ * g / 2;
-                        // time graph replays of a resident batch: device time only
-                        void* pb = nullptr;
-                        st = bmmc_batch_create(descs, count, &o, &pb);
+                        double per;
+                        st = time_batch(o, &per);
                         if (st != BMMC_OK) return st;
-                        bmmc_batch_launch(pb, stream);  // warm-up
-                        hipEventRecord(tm.a, stream);
-                        for (int r = 0; r < reps; r++) bmmc_batch_launch(pb, stream);
-                        hipEventRecord(tm.b, stream);
-                        hipEventSynchronize(tm.b);
-                        bmmc_batch_destroy(pb);
-                        float ms = 0;
-                        hipEventElapsedTime(&ms, tm.a, tm.b);
-                        const double per = ms / reps;
                         if (per < best) {
                             best = per;
                             bo = o;
@@ -488,6 +500,20 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
                     }
                 }
             }
+        }
+    }
+    // then the tile order of the best: XOR-mixed selection, or neighbouring
+    // tiles writing neighbouring runs for k of the tile-index bits
+    const bmmc_batch_options_t base = bo;
+    for (int to : {2, 4 + 16 * 2, 4 + 16 * 4, 4 + 16 * 6, 4 + 16 * 7, 4 + 16 * 8, 4 + 16 * 15}) {
+        bmmc_batch_options_t o = base;
+        o.tile_order = to;
+        double per;
+        st = time_batch(o, &per);
+        if (st != BMMC_OK) return st;
+        if (per < best) {
+            best = per;
+            bo = o;
         }
     }
     {

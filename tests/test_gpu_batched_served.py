@@ -53,12 +53,14 @@ def test_batched_mixed_sizes_and_widths(order, use_graph, hints, method):
     check_all(arrays)
 
 
+@pytest.mark.parametrize("tile_order", [0, 2, 4 + 16 * 7])
 @pytest.mark.parametrize("iters", [4, 8])
 @pytest.mark.parametrize("chunk", [1, 4, 16])
-def test_batched_chunks_and_grid(chunk, iters):
+def test_batched_chunks_and_grid(chunk, iters, tile_order):
     sizes = gen.batched_sizes(40, chunk, 10, 20)
     arrays = make_batch(sizes, [4, 8, 16, 4] * (len(sizes) // 4), chunk)
-    B.bmmc_permute_batched(items(arrays), G.stream(), {"chunk_tiles": chunk, "workgroups": 64, "iters": iters})
+    B.bmmc_permute_batched(items(arrays), G.stream(), {"chunk_tiles": chunk, "workgroups": 64, "iters": iters,
+                                                       "tile_order": tile_order})
     G.sync()
     check_all(arrays)
 

@@ -427,6 +427,36 @@ def test_tune_cache_classes_round_trip(tmp_path):
     assert len(saved) == 2 and '"class": 1, "used": 1' in saved[1]
 
 
+def test_tune_cache_batch_lines_with_and_without_tile_order(tmp_path):
+    """Batch entries load with a tile order and in the older form without
+    one (tile order 0), and are saved with it."""
+    path = tmp_path / "batch.jsonl"
+    lines = [
+        '{"kind": "batch", "sig": "00000000000000a1", "workgroups": 512, "chunk_tiles": 2, "order": 0, '
+        '"method": 0, "iters": 8, "tile_order": 116, "ms": 0.5}',
+        '{"kind": "batch", "sig": "00000000000000a2", "workgroups": 1024, "chunk_tiles": 4, "order": 1, '
+        '"method": 1, "iters": 4, "ms": 0.75}',
+    ]
+    path.write_text("\n".join(lines) + "\n")
+    assert B.bmmc_tune_load(str(path)) == 2
+    out = tmp_path / "again.jsonl"
+    B.bmmc_tune_save(str(out))
+    saved = {l.split('"sig": "')[1][:16]: l for l in out.read_text().splitlines() if '"kind": "batch"' in l}
+    assert '"tile_order": 116' in saved["00000000000000a1"]
+    assert '"tile_order": 0' in saved["00000000000000a2"] and '"chunk_tiles": 4' in saved["00000000000000a2"]
+
+
+def test_batch_options_validated():
+    """Options are checked before any device work (addresses are never
+    dereferenced: the call fails first)."""
+    rows, c = gen.random_bmmc(12, 1)
+    item = (1 << 32, (1 << 32) + (1 << 20), 12, 4, rows, c)
+    with pytest.raises(B.BmmcError, match="tile_order"):
+        B.bmmc_permute_batched([item], None, {"tile_order": 256})
+    with pytest.raises(B.BmmcError, match="iters"):
+        B.bmmc_permute_batched([item], None, {"iters": 2})
+
+
 @pytest.mark.skipif("BMMC_TUNE_CACHE" in os.environ, reason="another tuning file is named")
 def test_packaged_tuning_results_are_loaded():
     """The library starts from its shipped gfx950 tuning results: the default
