@@ -118,11 +118,13 @@ def kernel_key(name):
     return base.replace(" ", "")
 
 
-def write_traffic(fetch_dir, write_dir, nbytes):
-    """profiles/traffic.json from two rocprofv3 --pmc runs of this benchmark
-    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled
-    by the ratio (algorithmic bytes / counter bytes) it shows for the plain
-    copy kernel k_copy<4,0>, which reads and writes `nbytes` per launch."""
+def write_traffic(fetch_dir, write_dir, nbytes, workload):
+    """profiles/traffic.json, entry `workload`, from two rocprofv3 --pmc runs
+    of this benchmark on that workload (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch).  Each counter is scaled by the ratio (algorithmic bytes /
+    counter bytes) it shows for the plain copy kernel k_copy<4,0>, which
+    reads and writes `nbytes` per launch.  Entries of other workloads are
+    kept while the kernel source is unchanged."""
     import csv
     import glob
     import statistics
@@ -143,23 +145,28 @@ def write_traffic(fetch_dir, write_dir, nbytes):
         rb, wb = fetch[k] * f_scale, write[k] * w_scale
         kernels[k] = {"read_bytes_per_launch": round(rb), "write_bytes_per_launch": round(wb),
                       "bytes_per_launch": round(rb + wb)}
-    rec = {"kernel_source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
-           "calibration": "k_copy<4,0> moving %d bytes each way" % nbytes, "kernels": kernels}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    if rec.get("kernel_source_hash") != kernel_source_hash() or "workloads" not in rec:
+        rec = {"kernel_source_hash": kernel_source_hash(), "workloads": {}}
+    rec["workloads"][workload] = {"fetch_scale": f_scale, "write_scale": w_scale,
+                                  "calibration": "k_copy<4,0> moving %d bytes each way" % nbytes,
+                                  "kernels": kernels}
+    with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch measured with rocprofv3 counters, if they were taken
-    on the current kernel source (else None)."""
+def traffic_for(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` measured with rocprofv3
+    counters, if they were taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    ent = rec.get("kernels", {}).get(kernel)
+    ent = rec.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel)
     return ent.get("bytes_per_launch") if ent else None
 
 
@@ -577,7 +584,8 @@ def main():
         return
     if args.traffic_from:
         n, w = WORKLOADS[args.workload][:2]
-        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w), indent=1))
+        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w, args.workload),
+                         indent=1))
         return
 
     if args.gpus != 1:
@@ -692,7 +700,7 @@ def main():
     per_launch_ms = ms / launches_per_step if len(kstats) == 1 else events_ms
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    tbytes = traffic_for(dname)
+    tbytes = traffic_for(args.workload, dname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 # HBM bytes per launch from the rocprofv3 counters, as a rate over the same launch time

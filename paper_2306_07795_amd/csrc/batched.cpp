@@ -27,10 +27,11 @@ struct BatchState {
     void* host = nullptr;  // pinned staging of the same layout
     size_t cap_passes = 0, cap_items = 0;
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
-    // one captured graph per (cache hints, tile iterations) setting (batches
-    // of different sizes alternate between them), each for one grid size
-    hipGraphExec_t exec[8] = {};
-    uint32_t exec_grid[8] = {};
+    // one captured graph per (cache hints, tile iterations, second phase)
+    // setting (batches of different sizes alternate between them), each for
+    // one grid size
+    hipGraphExec_t exec[16] = {};
+    uint32_t exec_grid[16] = {};
 };
 
 struct BatchRegistry {
@@ -105,21 +106,24 @@ BatchState* batch_state(hipStream_t stream, int device) {
     return bs;
 }
 
-// Enqueue [clear heads] -> phase 0 -> phase 1 on `s` (captured or not) for
-// the device table at d with layout L.
-hipError_t enqueue_phases_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, hipStream_t s) {
+// Enqueue [clear heads] -> phase 0 [-> phase 1] on `s` (captured or not) for
+// the device table at d with layout L; phase 1 only when some array takes
+// two passes.
+hipError_t enqueue_phases_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, bool second,
+                             hipStream_t s) {
     uint32_t* heads = (uint32_t*)(d + L.heads_off);
     const BatchPass* passes = (const BatchPass*)(d + L.passes_off);
     const BatchItem* items = (const BatchItem*)(d + L.items_off);
     const uint32_t* range = (const uint32_t*)d;
     hipError_t e = launch_zero(heads, 2, s);
     if (e == hipSuccess) e = launch_batched(passes, items, range, 0, heads, grid, hints, iters, s);
-    if (e == hipSuccess) e = launch_batched(passes, items, range, 1, heads + 1, grid, hints, iters, s);
+    if (e == hipSuccess && second) e = launch_batched(passes, items, range, 1, heads + 1, grid, hints, iters, s);
     return e;
 }
 
-// Capture the three launches into an executable graph.
-int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, hipGraphExec_t* out) {
+// Capture those launches into an executable graph.
+int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int iters, bool second,
+                     hipGraphExec_t* out) {
     hipStream_t cap;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -128,7 +132,7 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int 
         hipStreamDestroy(cap);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    enqueue_phases_at(d, L, grid, hints, iters, cap);
+    enqueue_phases_at(d, L, grid, hints, iters, second, cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
     hipStreamDestroy(cap);
@@ -142,15 +146,18 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int 
     return BMMC_OK;
 }
 
-int build_graph(BatchState* bs, uint32_t grid, int hints, int iters) {
-    const int slot = (hints & 3) | (iters == 8 ? 4 : 0);
+int graph_slot(int hints, int iters, bool second) { return (hints & 3) | (iters == 8 ? 4 : 0) | (second ? 8 : 0); }
+
+int build_graph(BatchState* bs, uint32_t grid, int hints, int iters, bool second) {
+    const int slot = graph_slot(hints, iters, second);
     hipGraphExec_t& g = bs->exec[slot];
     if (g && bs->exec_grid[slot] == grid) return BMMC_OK;
     if (g) {
         hipGraphExecDestroy(g);
         g = nullptr;
     }
-    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, iters, &g);
+    int st = capture_graph_at((uint8_t*)bs->dev, layout_for(bs->cap_passes, bs->cap_items), grid, hints, iters,
+                              second, &g);
     if (st != BMMC_OK) return st;
     bs->exec_grid[slot] = grid;
     return BMMC_OK;
@@ -350,23 +357,24 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
 
     const int iters = batched_iters(o.iters);
     uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(iters));
+    const uint32_t* range = (const uint32_t*)h;
+    const bool second = range[2] > range[1];
     if (o.use_graph < 0) {
         // plain launches: no more work-groups than the larger phase has items
-        const uint32_t* range = (const uint32_t*)h;
         const uint32_t most = std::max(range[1] - range[0], range[2] - range[1]);
         grid = std::max(1u, std::min(grid, most));
     }
     const int hints = resolve_batch_hints(o, moved);
     if (o.use_graph >= 0) {
-        st = build_graph(bs, grid, hints, iters);
+        st = build_graph(bs, grid, hints, iters, second);
         if (st != BMMC_OK) return st;
     }
     LaunchScope ls(ds, stream, "k_batched", moved);
     if (o.use_graph >= 0) {
-        e = hipGraphLaunch(bs->exec[(hints & 3) | (iters == 8 ? 4 : 0)], stream);
+        e = hipGraphLaunch(bs->exec[graph_slot(hints, iters, second)], stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, iters, stream);
+        e = enqueue_phases_at((uint8_t*)bs->dev, L, grid, hints, iters, second, stream);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     return BMMC_OK;
@@ -448,6 +456,7 @@ struct PreparedBatch {
     int hints = 0;
     int iters = 4;
     bool use_graph = true;
+    bool second = false;  // some array takes two passes
     Layout L{};
     double moved = 0;
 };
@@ -510,6 +519,10 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     std::vector<uint8_t> image(pb->L.total, 0);
     size_t ni;
     fill_table(pb->arrays, work, chunk, image.data(), pb->L, &ni, &pb->moved);
+    {
+        const uint32_t* range = (const uint32_t*)image.data();
+        pb->second = range[2] > range[1];
+    }
     hipError_t e = hipMalloc(&pb->table, pb->L.total);
     if (e != hipSuccess) {
         pb->table = nullptr;
@@ -523,7 +536,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     pb->hints = resolve_batch_hints(o, pb->moved);
     pb->use_graph = o.use_graph >= 0;
     if (!work.empty() && pb->use_graph) {
-        st = capture_graph_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters, &pb->exec);
+        st = capture_graph_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters, pb->second, &pb->exec);
         if (st != BMMC_OK) return fail(st);
     }
     *handle_out = pb;
@@ -538,7 +551,7 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     std::lock_guard<std::mutex> lk(ds->mu);
     for (auto& ba : pb->arrays) {
         if (!ba.single) continue;
-        int st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, stream, 0);
+        int st = enqueue_plan(ds, *ba.plan, ba.in, ba.out, stream, ba.grid, ba.hints, ba.order, ba.scratch);
         if (st != BMMC_OK) return st;
     }
     bool any = false;
@@ -547,7 +560,7 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     LaunchScope ls(ds, stream, "k_batched", pb->moved);
     hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
                                  : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters,
-                                                     stream);
+                                                     pb->second, stream);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "batch launch");
 }
 
