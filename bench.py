@@ -273,6 +273,21 @@ def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, reps=20):
     return out
 
 
+def other_matrices(x, y, n, w, copy_ms, stream, seeds=8, reps=10):
+    """The library's default call on random matrices of seeds 0..seeds-1 (the
+    timed workload is seed 0): beyond the last-level cache how the accesses
+    meet the memory system varies from one matrix to another."""
+    from paper_2306_07795_amd import binding as B
+    from synth import gen
+    pct = []
+    for seed in range(seeds):
+        rows, c = gen.random_bmmc(n, seed)
+        ms = timed(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream)
+        pct.append(100.0 * copy_ms / ms)
+    return {"seeds": f"0-{seeds - 1}", "pct_of_device_copy": [round(p, 1) for p in pct],
+            "mean": round(sum(pct) / len(pct), 1), "min": round(min(pct), 1), "max": round(max(pct), 1)}
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -689,6 +704,8 @@ def main():
                                                   retune=args.retune)
         extras["cache_state"] = cache_states(x, y, n, rows, c, w, opts, extras["paper_two_pass"]["options"],
                                              stream)
+        if kind == "random":
+            extras["random_matrices"] = other_matrices(x, y, n, w, copy_ms, stream)
 
     # roofline of the dominant kernel: algorithmic bytes per launch / mean
     # launch time.  When every launch of a step is that kernel, the mean

@@ -360,11 +360,15 @@ int bmmc_batch_destroy(void* handle);
 /* Time the available tile shapes (threads x iterations), run widths, cache
    hints, tile orders and grid sizes (with BMMC_METHOD_AUTO also the two-pass
    scheme) on 2^n elements of elem_bytes bytes, `reps` timed runs each, on
-   `stream` (synchronizes it), for two classes of matrices: a random matrix
-   (class 0: not tiled) and a random bit permutation (class 1: tiled).  The
+   `stream` (synchronizes it), for two classes of matrices: random matrices
+   (class 0: not tiled; three, six from 256 MiB on) and three bit
+   permutations (class 1: tiled; a random one, the bit reversal, the
+   half-split transpose), times summed.  The
    fastest of each class is cached for (n, elem_bytes, method, class) and used
    by later calls that pass no options, by the class of their matrix; class
-   0's is also returned.  Allocates two temporary buffers of 2^n * elem_bytes.
+   0's is also returned.  Below 64 MiB the `reps` calls of a candidate are
+   captured into a graph (on a stream of its own) and the replay is timed.
+   Allocates two temporary buffers of 2^n * elem_bytes.
    Errors: _RANGE, _ARG, _NOMEM, _HIP. */
 int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
                   bmmc_options_t* best_out, double* best_ms);

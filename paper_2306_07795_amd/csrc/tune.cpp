@@ -5,6 +5,7 @@
 // batch signature for batched launches.  The cache can be saved to and loaded
 // from a JSON-lines file; BMMC_TUNE_CACHE names a file loaded on first use.
 #include <algorithm>
+#include <cmath>
 #include <dlfcn.h>
 
 #include <cinttypes>
@@ -246,15 +247,44 @@ struct TuneMatrix {
     uint64_t c;
 };
 
-// Mean time of one call with options o, summed over the matrices.
+// Mean time of one call with options o, summed over the matrices.  Arrays
+// below 64 MiB run for a few microseconds, less than the host takes to
+// issue a call: their `reps` calls are captured into a graph (on `cap`,
+// where a first call outside the capture has made any scratch) and the
+// graph's replay is timed, so that device time is what is compared.
 double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, const bmmc_options_t& o,
-                    const void* in, void* out, hipStream_t stream, int reps, Timer& tm) {
+                    const void* in, void* out, hipStream_t stream, hipStream_t cap, int reps, Timer& tm) {
     double total = 0;
+    const bool graph = cap && ((size_t)1 << n) * (size_t)elem_bytes < ((size_t)64 << 20);
     for (const TuneMatrix& m : mats) {
-        if (bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream) != BMMC_OK) return -1;
-        hipEventRecord(tm.a, stream);
-        for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream);
-        hipEventRecord(tm.b, stream);
+        if (!graph) {
+            if (bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream) != BMMC_OK) return -1;
+            hipEventRecord(tm.a, stream);
+            for (int r = 0; r < reps; r++) bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream);
+            hipEventRecord(tm.b, stream);
+        } else {
+            if (bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, cap) != BMMC_OK) return -1;
+            if (hipStreamSynchronize(cap) != hipSuccess) return -1;
+            if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
+            int st = BMMC_OK;
+            for (int r = 0; r < reps && st == BMMC_OK; r++)
+                st = bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, cap);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(cap, &g);
+            hipGraphExec_t x = nullptr;
+            if (st != BMMC_OK || e != hipSuccess || hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                (void)hipGetLastError();
+                return -1;
+            }
+            hipGraphDestroy(g);
+            hipGraphLaunch(x, stream);  // warm-up
+            hipEventRecord(tm.a, stream);
+            hipGraphLaunch(x, stream);
+            hipEventRecord(tm.b, stream);
+            hipEventSynchronize(tm.b);
+            hipGraphExecDestroy(x);
+        }
         hipEventSynchronize(tm.b);
         float ms = 0;
         hipEventElapsedTime(&ms, tm.a, tm.b);
@@ -271,7 +301,7 @@ double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, 
 void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with_tiled,
                    const std::vector<TuneMatrix>& mats, const void* in, void* out, hipStream_t stream, int reps,
                    bmmc_options_t* bo, double* best) {
-    static const int kShapes[][2] = {{256, 4}, {256, 8}, {512, 4}, {512, 8}, {1024, 4}, {256, 16}};
+    static const int kShapes[][2] = {{256, 2}, {512, 2}, {256, 4}, {256, 8}, {512, 4}, {512, 8}, {1024, 4}, {256, 16}};
     // tile orders: plain, and neighbouring tiles writing neighbouring runs
     // for the 7 lowest tile-index bits (best for most large arrays)
     static const int kStage1Orders[] = {4, 4 + 16 * 7};
@@ -279,6 +309,11 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
     const size_t kBases = 6, kFinal = 8;
     std::vector<std::pair<double, bmmc_options_t>> timed;
     Timer tm;
+    hipStream_t cap = nullptr;  // capture stream of the graph timing
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        cap = nullptr;
+        (void)hipGetLastError();
+    }
     const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
     // non-temporal stores (2) or loads and stores (3) beyond the last-level
     // cache, none (4) or stores only below it
@@ -288,7 +323,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
         return ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
     };
     auto run = [&](const bmmc_options_t& o) {
-        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, reps, tm);
+        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm);
         if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
     };
     {
@@ -364,14 +399,17 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
     *best = 1e30;
     std::memset(bo, 0, sizeof(*bo));
     std::sort(timed.begin(), timed.end(), by_time);
-    // the fastest few again, in two interleaved rounds of twice the runs
-    // (the better of each candidate's two), so that drift and noise do not
-    // pick the winner
+    // the fastest few again, in three interleaved rounds of at least 5 ms
+    // of calls each (the best of each candidate's three), so that drift and
+    // noise do not pick the winner among settings a percent apart
     const size_t keep = timed.size() < kFinal ? timed.size() : kFinal;
     std::vector<double> again(keep, 1e30);
-    for (int round = 0; round < 2; round++)
+    for (int round = 0; round < 3; round++)
         for (size_t i = 0; i < keep; i++) {
-            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, reps * 2, tm);
+            const double per_call = timed[i].first / (double)mats.size();
+            int r = (int)std::ceil(5.0 / (per_call > 1e-4 ? per_call : 1e-4));
+            r = std::max(reps * 2, std::min(r, 200));
+            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm);
             if (t > 0 && t < again[i]) again[i] = t;
         }
     for (size_t i = 0; i < keep; i++)
@@ -380,6 +418,18 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
             *bo = timed[i].second;
         }
     if (*best < 1e30) *best /= (double)mats.size();
+    if (cap) {
+        hipStreamSynchronize(cap);
+        {
+            std::lock_guard<std::mutex> lk(ds->mu);
+            auto it = ds->scratch.find(cap);
+            if (it != ds->scratch.end()) {
+                if (it->second.ptr) hipFree(it->second.ptr);
+                ds->scratch.erase(it);
+            }
+        }
+        hipStreamDestroy(cap);
+    }
 }
 
 }  // namespace
@@ -409,12 +459,17 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
     bmmc_options_t bo[2];
     double best[2];
     for (int cls = 0; cls < 2; cls++) {
-        // class 0: a random matrix; class 1: three bit permutations -- a
-        // random one, the bit reversal and the transpose of the half split --
-        // so that one setting serves the usual tiled matrices
-        std::vector<TuneMatrix> mats(cls == 0 ? 1 : 3);
+        // class 0: how a setting's accesses meet the memory system varies
+        // from one random matrix to another, most beyond the last-level
+        // cache (a spread of 10 % of the copy's rate at 1 GiB): three random
+        // matrices, six from 256 MiB on.  Class 1: three bit permutations --
+        // a random one, the bit reversal and the transpose of the half split
+        // -- so that one setting serves the usual tiled matrices.
+        const int nrand = bytes >= ((size_t)256 << 20) ? 6 : 3;
+        std::vector<TuneMatrix> mats(cls == 0 ? nrand : 3);
         if (cls == 0) {
-            random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n, mats[0].rows, &mats[0].c);
+            for (int k = 0; k < nrand; k++)
+                random_matrix(n, 0xA5A5A5A5ull + (uint64_t)n + ((uint64_t)k << 40), mats[k].rows, &mats[k].c);
         } else {
             random_bpc(n, 0x5A5A5A5Aull + (uint64_t)n, mats[0].rows, &mats[0].c);
             for (int i = 0; i < n; i++) {

@@ -27,7 +27,9 @@ def main():
     ap.add_argument("--min-n", type=int, default=12, help="smallest n")
     ap.add_argument("--tiled-from-log2", type=int, default=24,
                     help="also tune the two-pass scheme from arrays of 2^this bytes")
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=3, help="timed calls per candidate from 64 MiB on")
+    ap.add_argument("--reps-small", type=int, default=20,
+                    help="timed calls per candidate below 64 MiB (captured into one graph)")
     args = ap.parse_args()
     if os.environ.get("BMMC_TUNE_CACHE", None) != "":
         print("note: BMMC_TUNE_CACHE is not empty; the entries of that file are kept", flush=True)
@@ -37,9 +39,10 @@ def main():
             methods = [B.METHOD_AUTO]
             if n + lw >= args.tiled_from_log2:
                 methods.append(B.METHOD_TILED)
+            reps = args.reps if (1 << (n + lw)) >= (64 << 20) else args.reps_small
             for m in methods:
                 t0 = time.time()
-                opts, ms = B.bmmc_autotune(n, w, m, None, args.reps)
+                opts, ms = B.bmmc_autotune(n, w, m, None, reps)
                 gbps = 2.0 * (1 << n) * w / (ms * 1e-3) / 1e9
                 print(f"n={n} w={w} method={m}: {ms:.4f} ms ({gbps:.0f} GB/s) in {time.time() - t0:.1f} s  {opts}",
                       flush=True)

@@ -141,6 +141,23 @@ def test_autotune_small_then_permute():
         assert np.array_equal(G.to_host(y, a), O.permute(a, 18, rows, c))
 
 
+def test_autotune_tiled_method_small():
+    """The paper's two-pass scheme tuned below 64 MiB (its candidates timed as
+    graph replays, scratch made before the capture); the tuned options then
+    permute correctly."""
+    n = 17
+    opts, ms = B.bmmc_autotune(n, 8, B.METHOD_TILED, G.stream(), 2)
+    assert ms > 0
+    rows, c = gen.random_bmmc(n, 12)
+    tuned = B.bmmc_tune_lookup(n, 8, rows, B.METHOD_TILED)
+    assert tuned is not None and tuned["method"] == B.METHOD_TILED
+    a = gen.data(n, 8, 12)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    B.bmmc_permute_ex(x, y, n, rows, c, 8, tuned, G.stream())
+    G.sync()
+    assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
+
+
 def test_autotune_batched_small():
     sizes = gen.batched_sizes(20, 11, 10, 16)
     arrays = make_batch(sizes, [4] * 20, 11)
