@@ -215,7 +215,7 @@ bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc
     if (!e.hints) e.hints = d->hints;
     if (!e.tile_order) e.tile_order = d->order;
     if (!e.grid && d->persistent && ds && ds->cu_count > 0) {
-        KernelShape ks = default_shape(w);
+        KernelShape ks = general_shape(w);  // the general tile's shape unless given
         ks.nt = e.threads ? e.threads : ks.nt;
         ks.iters = e.iters ? e.iters : ks.iters;
         const int occ = tiled_occupancy(w, ks.nt, ks.iters, 0);
