@@ -350,10 +350,19 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
 
     sep = lat(separate, max(5, reps // 5))
     pb.close()
+    # the copy bound at the batch's size: one copy of as many bytes (the
+    # batch's 2.6 GB each way do not fit the last-level cache, unlike the
+    # default workload's 256 MiB)
+    cx = torch.empty(total, dtype=torch.uint8, device="cuda")
+    cy = torch.empty_like(cx)
+    copy_ms, copy_how = best_device_copy(cx, cy, total, stream)
+    del cx, cy
     med = float(np.median(resident))
     return {
         "arrays": count, "bytes_per_side": total,
         "GBps": round(gbps(total, med), 1),
+        "device_copy_same_bytes_GBps": round(gbps(total, copy_ms), 1),
+        "pct_of_device_copy_same_bytes": round(100.0 * copy_ms / med, 1),
         "p50_ms": round(med, 4), "p99_ms": round(float(np.percentile(resident, 99)), 4),
         "oneshot_p50_ms": round(float(np.median(oneshot)), 4),
         "oneshot_GBps": round(gbps(total, float(np.median(oneshot))), 1),
