@@ -97,7 +97,10 @@ typedef struct {
     int run_out;   /* write-run bits (output runs of 2^run_out elements); 0 = t */
     /* 1: non-temporal loads, 2: non-temporal stores, 3: both, 4: neither;
        0: library default (size-dependent as above, else both for arrays of
-       64 MiB and more, neither below). */
+       64 MiB and more, neither below).  Adding 8 (two-pass plans): the
+       scratch array goes through the caches -- cached stores in the first
+       pass, cached loads in the second, so that the second pass finds it in
+       the 256 MB last-level cache; the default for arrays up to 256 MiB. */
     int hints;
     /* 1: give each XCD a contiguous range of tiles (work-groups are dealt
        to the XCDs round-robin); 2: select tiles through XOR-combined index

@@ -253,9 +253,14 @@ PlanOptions plan_options(const bmmc_options_t* o, int w) {
 
 int resolve_hints(const bmmc_options_t* o, size_t bytes) {
     const int h = o ? o->hints : 0;
-    if (h == 0) return bytes >= ((size_t)64 << 20) ? 3 : 0;
-    if (h & 4) return 0;
-    return h & 3;
+    const int scratch_cached = h & 8;
+    const int base = h & ~8;
+    // default: non-temporal loads and stores from 64 MiB; a two-pass plan's
+    // scratch through the caches while it fits the 256 MB last-level cache
+    if (base == 0)
+        return (bytes >= ((size_t)64 << 20) ? 3 : 0) | (bytes <= ((size_t)256 << 20) ? 8 : 0) | scratch_cached;
+    if (base & 4) return scratch_cached;
+    return (base & 3) | scratch_cached;
 }
 
 int resolve_order(const bmmc_options_t* o) {
@@ -290,9 +295,9 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "naive launch");
     }
     const KernelShape& ks = plan.shape;
-    if (!tiled_kernel_available(plan.w, ks.nt, ks.iters, hints))
+    if (!tiled_kernel_available(plan.w, ks.nt, ks.iters, hints & 3))
         return set_error(BMMC_ERR_RANGE, "no tiled kernel for w=%d threads=%d iters=%d hints=%d", plan.w, ks.nt,
-                         ks.iters, hints);
+                         ks.iters, hints & 3);
     void* mid = scratch;
     if (plan.npass == 2 && !mid) {
         int st = get_scratch(ds, stream, bytes, &mid);
@@ -304,9 +309,14 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
         const void* src = (k == 0) ? in : mid;
         void* dst = (k == plan.npass - 1) ? out : mid;
         const uint32_t ntiles = 1u << tab.ntb;
-        kernel_name(name, sizeof(name), plan, hints);
+        // hints bit 8 (two passes): the scratch array goes through the
+        // caches -- cached stores in the first pass, cached loads in the
+        // second -- so that the second pass finds what fits of it there
+        int hk = hints & 3;
+        if ((hints & 8) && plan.npass == 2) hk &= (k == 0) ? 1 : 2;
+        kernel_name(name, sizeof(name), plan, hk);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
-        e = launch_tiled(plan.w, ks.nt, ks.iters, hints, src, dst, tab, ntiles, grid,
+        e = launch_tiled(plan.w, ks.nt, ks.iters, hk, src, dst, tab, ntiles, grid,
                          (order & 1) ? (uint32_t)ds->xcds : 0u, stream);
         if (e != hipSuccess) return hip_fail(e, "tiled launch");
     }

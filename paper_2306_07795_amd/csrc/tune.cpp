@@ -347,7 +347,9 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
             for (int a = lo; sum - a >= lo; a++) {
                 const int b = sum - a;
                 for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
-                    for (int hi = 0; hi < 2; hi++) {
+                    const bool two = m == 1 || method == BMMC_METHOD_TILED;
+                    // two-pass plans also with the scratch kept in the caches
+                    for (int hi = 0; hi < (two ? 4 : 2); hi++) {
                         for (int order : kStage1Orders) {
                             for (int g = 0; g < 2; g++) {
                                 bmmc_options_t o;
@@ -360,7 +362,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
                                 o.threads = ks.nt;
                                 o.iters = ks.iters;
                                 o.swizzle = 1;
-                                o.hints = hints_of[hi];
+                                o.hints = hints_of[hi & 1] | (hi >= 2 ? 8 : 0);
                                 o.tile_order = order;
                                 o.grid = g == 0 ? -1 : persistent_grid(o);
                                 run(o);

@@ -111,6 +111,7 @@ def test_onepass_method(n, w):
     {"swizzle": -1}, {"grid": 64}, {"grid": 1}, {"threads": 256, "iters": 16, "t": 7},
     {"run_in": 7, "run_out": 6, "threads": 512, "iters": 8, "tile_order": 2, "hints": 3},
     {"tile_order": 4 + 16 * 15, "grid": -1}, {"tile_order": 1 + 16 * 6, "grid": 96},
+    {"hints": 3 | 8}, {"hints": 2 | 8, "threads": 512, "iters": 4}, {"hints": 4 | 8},
     {"threads": 1024, "iters": 4, "run_in": 6, "run_out": 8, "tile_order": 4 + 16 * 7, "hints": 3},
 ])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
