@@ -540,6 +540,18 @@ def bmmc_server_submit(handle, inp, out, n: int, A_rows, c: int, elem_bytes: int
     return int(ticket.value)
 
 
+def bmmc_server_submit_many(handle, descs: "DescBatch", arrival_ns) -> list:
+    """Submit every descriptor of a DescBatch (marshalled beforehand), the
+    k-th arriving at arrival_ns[k]; one library call each, tickets in order."""
+    L = lib()
+    ticket = _i64(0)
+    out = []
+    for k in range(descs.count):
+        _check(L.bmmc_server_submit(handle, _c.byref(descs.arr[k]), int(arrival_ns[k]), _c.byref(ticket)))
+        out.append(int(ticket.value))
+    return out
+
+
 def bmmc_server_poll(handle, ticket: int, wait: bool = False):
     """None while pending; else (completion time ns, output device address)."""
     done = _i64(0)

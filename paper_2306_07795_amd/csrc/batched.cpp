@@ -243,6 +243,33 @@ int resolve_batch_hints(const bmmc_batch_options_t& o, double moved) {
 
 }  // namespace
 
+int reserve_batch_state(hipStream_t stream, int device, size_t passes, size_t items) {
+    return ensure_capacity(batch_state(stream, device), passes, items);
+}
+
+void release_batch_state(hipStream_t stream, int device) {
+    BatchState* bs = nullptr;
+    {
+        auto& r = registry();
+        std::lock_guard<std::mutex> lk(r.mu);
+        for (size_t i = 0; i < r.states.size(); i++)
+            if (r.states[i]->stream == stream && r.devices[i] == device) {
+                bs = r.states[i];
+                r.states.erase(r.states.begin() + (long)i);
+                r.devices.erase(r.devices.begin() + (long)i);
+                break;
+            }
+    }
+    if (!bs) return;
+    for (hipGraphExec_t& g : bs->exec)
+        if (g) hipGraphExecDestroy(g);
+    if (bs->staged) hipEventSynchronize(bs->staged);
+    if (bs->dev) hipFree(bs->dev);
+    if (bs->host) hipHostFree(bs->host);
+    if (bs->staged) hipEventDestroy(bs->staged);
+    delete bs;
+}
+
 int batch_validate(const bmmc_desc_t* descs, int count) {
     if (count < 0 || (count > 0 && !descs)) return set_error(BMMC_ERR_ARG, "descs is NULL or count < 0");
     struct Iv {

@@ -111,9 +111,15 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
             default: return set_error(st, "planner failed (%d)", st);
         }
     }
-    std::lock_guard<std::mutex> lk(ds->mu);
-    if (ds->plans.size() > 8192) ds->plans.clear();
-    ds->plans[key] = plan;
+    // A full cache is emptied by swapping it out under the lock and freeing
+    // its plans after the lock is released: launches on other threads wait
+    // for this lock, and freeing thousands of plans takes milliseconds.
+    decltype(ds->plans) old;
+    {
+        std::lock_guard<std::mutex> lk(ds->mu);
+        if (ds->plans.size() > 8192) old.swap(ds->plans);
+        ds->plans[key] = plan;
+    }
     *out = plan;
     return BMMC_OK;
 }

@@ -115,6 +115,12 @@ int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchAr
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream);
 uint64_t batch_signature(const bmmc_desc_t* descs, int count);
+// Size the batch table and its pinned staging of `stream` for at least this
+// many passes and work items now, so that later batched launches on it do
+// not allocate (caller holds ds->mu or owns the stream).
+int reserve_batch_state(hipStream_t stream, int device, size_t passes, size_t items);
+// Free the batch table of `stream` (its work must have completed).
+void release_batch_state(hipStream_t stream, int device);
 
 // Tuning cache lookups (tune.cpp); false when nothing is cached.
 // Matrix class of the tuning cache: 1 for a matrix tiled at the default run

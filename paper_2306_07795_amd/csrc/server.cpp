@@ -401,6 +401,13 @@ extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** hand
     for (Slot& sl : s->slots) {
         hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        // the batch table of each stream made now: allocating it (device
+        // memory, pinned staging) while serving would stall every stream
+        const int st2 = reserve_batch_state(sl.stream, ds->device, 128, 8192);
+        if (st2 != BMMC_OK) {
+            bmmc_server_destroy(s);
+            return st2;
+        }
     }
     // Planning a random BMMC costs tens of microseconds; at tens of
     // thousands of requests per second several planners keep up.
@@ -550,11 +557,13 @@ extern "C" int bmmc_server_destroy(void* handle) {
         s->cv_work.notify_all();
     }
     for (auto& t : s->planners) t.join();
-    s->dispatcher.join();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
     for (Slot& sl : s->slots) {
+        if (!sl.stream) continue;
         hipStreamSynchronize(sl.stream);
+        release_batch_state(sl.stream, s->device);
         hipStreamDestroy(sl.stream);
-        hipEventDestroy(sl.done);
+        if (sl.done) hipEventDestroy(sl.done);
     }
     hipFree(s->arena);
     for (auto& kv : s->table) delete kv.second;

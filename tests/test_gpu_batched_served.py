@@ -279,6 +279,37 @@ def test_prepared_batch_replays(method, iters):
         pb.close()
 
 
+def test_server_submit_many_in_arrival_order():
+    """Requests marshalled once and submitted together, each with its own
+    future arrival time, come out right."""
+    reqs = gen.poisson_requests(24, 20000.0, 17, n_lo=10, n_hi=18)
+    pool, items = {}, []
+    for r in reqs:
+        rows, c = gen.random_bmmc(r["n"], r["seed"])
+        a = gen.data(r["n"], r["w"], r["seed"])
+        x = G.to_device(a)
+        pool[r["id"]] = (rows, c, a, x)
+        items.append((x, None, r["n"], r["w"], rows, c))
+    srv = B.bmmc_server_create(1 << 28, streams=2, own_outputs=True)
+    try:
+        t0 = B.bmmc_server_now_ns() + 5_000_000
+        tickets = B.bmmc_server_submit_many(srv, B.DescBatch(items), [t0 + int(r["arrival"] * 1e9) for r in reqs])
+        assert len(tickets) == len(reqs) and len(set(tickets)) == len(reqs)
+        torch.cuda.synchronize()
+        B.bmmc_server_drain(srv)
+        for r, tk in zip(reqs, tickets):
+            done, out = B.bmmc_server_poll(srv, tk)
+            assert done >= t0 + int(r["arrival"] * 1e9)  # not before its arrival
+            rows, c, a, x = pool[r["id"]]
+            y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+            B.bmmc_copy(out, y, a.nbytes, G.stream())
+            G.sync()
+            assert np.array_equal(G.to_host(y, a), O.permute(a, r["n"], rows, c)), r
+            B.bmmc_server_release(srv, tk)
+    finally:
+        B.bmmc_server_destroy(srv)
+
+
 def test_server_stats_reset_after_warm_up():
     n, w = 16, 4
     srv = B.bmmc_server_create(1 << 28, streams=2, own_outputs=True)
