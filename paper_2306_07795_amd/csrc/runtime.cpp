@@ -5,6 +5,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <tuple>
+#include <map>
 
 #include "kernels.hpp"
 
@@ -194,6 +197,19 @@ const SizeDefault kSizeDefaults[] = {
 };
 }  // namespace
 
+// Resident work-groups per CU of a tiled kernel shape, asked of the runtime
+// once per shape (the answer does not change) rather than on every call.
+static int cached_occupancy(int w, int nt, int iters) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> known;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find({w, nt, iters});
+    if (it != known.end()) return it->second;
+    const int occ = tiled_occupancy(w, nt, iters, 0);
+    known[{w, nt, iters}] = occ;
+    return occ;
+}
+
 bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc_options_t* o) {
     bmmc_options_t e;
     if (o)
@@ -224,7 +240,7 @@ bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc
         KernelShape ks = general_shape(w);  // the general tile's shape unless given
         ks.nt = e.threads ? e.threads : ks.nt;
         ks.iters = e.iters ? e.iters : ks.iters;
-        const int occ = tiled_occupancy(w, ks.nt, ks.iters, 0);
+        const int occ = cached_occupancy(w, ks.nt, ks.iters);
         if (occ > 0) e.grid = 2 * ds->cu_count * occ;
     }
     return e;
