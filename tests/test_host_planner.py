@@ -340,6 +340,16 @@ def test_emulation_output_ordered_tiles(name, mk, w, method, order):
     assert st["write_lines"] == st["write_lines_min"]
 
 
+@pytest.mark.parametrize("order", [4 + 16 * 3, 4 + 16 * 15, 2 + 16 * 15])
+@pytest.mark.parametrize("n", [9, 12, 13, 14, 15])
+def test_output_ordered_tiles_with_few_tile_bits(n, order):
+    """k beyond the number of tile-selecting bits (the whole array in one
+    tile, or one or two tiles) is clamped to what there is."""
+    for rows, c in (gen.random_bmmc(n, 5 * n), (gen.bit_reversal_rows(n), 1)):
+        st = emulate_check(n, rows, c, 4, {"tile_order": order})
+        assert st["read_lines"] == st["read_lines_min"] and st["write_lines"] == st["write_lines_min"]
+
+
 @pytest.mark.parametrize("n,w,a,d", [
     (21, 4, 6, 13),   # 8 MiB: the general tile's own default
     (22, 4, 5, 13),   # 16 MiB: 256 x 8 vectors, 2^5-element reads
