@@ -202,6 +202,43 @@ def test_same_result_on_side_stream():
     assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c))
 
 
+def test_host_threads_on_their_own_streams():
+    """Four host threads call the library at once, each on a stream of its
+    own, each with new matrices (plans made concurrently), both methods (the
+    paper's scheme takes a scratch array per stream); every result checked."""
+    import threading
+    jobs = []
+    for t in range(4):
+        for k in range(12):
+            n = 10 + (7 * t + 3 * k) % 9
+            w = (4, 8)[(t + k) % 2]
+            rows, c = gen.random_bmmc(n, 1000 * t + k)
+            a = gen.data(n, w, 100 * t + k)
+            jobs.append((t, n, w, rows, c, a, G.to_device(a), G.empty_like_bytes(a),
+                         (B.METHOD_AUTO, B.METHOD_TILED)[k % 2]))
+    G.sync()
+    errors = []
+
+    def work(t):
+        try:
+            s = torch.cuda.Stream()
+            for (tt, n, w, rows, c, a, x, y, m) in jobs:
+                if tt == t:
+                    B.bmmc_permute_ex(x, y, n, rows, c, w, {"method": m}, s)
+            s.synchronize()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for (t, n, w, rows, c, a, x, y, m) in jobs:
+        assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c)), (t, n, w, m)
+
+
 @pytest.mark.parametrize("method,per_call", [(B.METHOD_AUTO, 1), (B.METHOD_TILED, 2)])
 def test_profile_reports_launches(method, per_call):
     n = 20
