@@ -294,7 +294,82 @@ struct NetMid {
     }
 };
 
-template <int NT, int ITERS, int OP>
+// The columns of a register group (see NetGroup): thread registers j and
+// j | 1 << K hold a pair; j keeps the smaller key when d0 XOR parity(q & j)
+// is 0.  Register indices are compile-time constants.
+template <int K, int OP>
+__device__ __forceinline__ void net_cx(uint32_t (&reg)[32], uint32_t q, uint32_t d0) {
+#pragma unroll
+    for (int jl = 0; jl < 32; jl++) {
+        if (jl & (1 << K)) continue;
+        const int jh = jl | (1 << K);
+        const uint32_t x = reg[jl], y = reg[jh];
+        const uint32_t mn = OP == 1 ? (uint32_t)min((int32_t)x, (int32_t)y) : min(x, y);
+        const uint32_t mx = OP == 1 ? (uint32_t)max((int32_t)x, (int32_t)y) : max(x, y);
+        const bool dir = ((d0 ^ (uint32_t)__builtin_popcount(q & (uint32_t)jl)) & 1u) != 0;
+        reg[jl] = dir ? mx : mn;
+        reg[jh] = dir ? mn : mx;
+    }
+}
+
+// Columns in register groups (2^13-slot tiles, 256 threads): per group, each
+// thread loads its 32 slots, runs the group's columns in registers and
+// stores them back; one barrier per group.
+template <int OP>
+struct NetMidRegs {
+    const NetColumns& C;
+    uint32_t* lds;
+    uint32_t tid;
+    template <typename PartsT>
+    __device__ __forceinline__ void operator()(const PartsT& pt) const {
+        for (uint32_t gi = 0; gi < C.ngroups; gi++) {
+            const NetGroup& G = C.grp[gi];
+            uint32_t base = 0;
+#pragma unroll
+            for (int b = 0; b < 8; b++) base |= ((tid >> b) & 1u) << ((G.cpos >> (4 * b)) & 15u);
+            // slots in Gray-code order: one XOR per step, one address live
+            uint32_t reg[32];
+            {
+                uint32_t sl = base;
+                reg[0] = lds[sl];
+#pragma unroll
+                for (int i = 1; i < 32; i++) {
+                    sl ^= G.S[__builtin_ctz(i)];
+                    reg[i ^ (i >> 1)] = lds[sl];
+                }
+            }
+            for (uint32_t i = G.first; i < G.last; i++) {
+                const NetCol c = C.col[i];
+                const uint32_t d0 =
+                    ((uint32_t)__builtin_popcount(c.g & pt.r) ^ (uint32_t)__builtin_popcount(c.beta & base)) & 1u;
+                const uint32_t q = c.rg >> 3;
+                switch (c.rg & 7u) {
+                    case 0: net_cx<0, OP>(reg, q, d0); break;
+                    case 1: net_cx<1, OP>(reg, q, d0); break;
+                    case 2: net_cx<2, OP>(reg, q, d0); break;
+                    case 3: net_cx<3, OP>(reg, q, d0); break;
+                    default: net_cx<4, OP>(reg, q, d0); break;
+                }
+            }
+            {
+                uint32_t sl = base;
+                lds[sl] = reg[0];
+#pragma unroll
+                for (int i = 1; i < 32; i++) {
+                    sl ^= G.S[__builtin_ctz(i)];
+                    lds[sl] = reg[i ^ (i >> 1)];
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// REGS: the columns in register groups (the host plans them only for the
+// full 2^13-slot tile of 256 threads); else each column through LDS.  Two
+// kernels, because the register groups need many more VGPRs, and so fewer
+// resident work-groups, than passes with few columns can afford.
+template <int NT, int ITERS, int OP, bool REGS>
 __global__ void __launch_bounds__(NT)
 k_tiled_net(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTables P, const NetColumns C,
             uint32_t ntiles, uint32_t xcds) {
@@ -302,18 +377,27 @@ k_tiled_net(const u32x4* __restrict__ in, u32x4* __restrict__ out, const PassTab
     __shared__ typename Ctx::E lds[1 << Ctx::D];
     Ctx ctx;
     ctx.init(P, threadIdx.x);
-    const NetMid<OP> mid{C, lds, 1u << (P.d - 1), threadIdx.x, NT};
-    ctx.run_tiles(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles, gridDim.x, threadIdx.x,
-                  mid);
+    if constexpr (REGS) {
+        static_assert(NT == 256 && Ctx::D == 13, "register groups are planned for 256 threads x 2^13 slots");
+        const NetMidRegs<OP> mid{C, lds, threadIdx.x};
+        ctx.run_tiles(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles, gridDim.x,
+                      threadIdx.x, mid);
+    } else {
+        const NetMid<OP> mid{C, lds, 1u << (P.d - 1), threadIdx.x, NT};
+        ctx.run_tiles(P, (const g_u32x4*)in, (g_u32x4*)out, lds, logical_block(xcds), ntiles, gridDim.x,
+                      threadIdx.x, mid);
+    }
 }
 
 struct TiledNetEntry {
     int nt, iters, op;
+    bool regs;
     void (*fn)(const u32x4*, u32x4*, const PassTables, const NetColumns, uint32_t, uint32_t);
 };
 static const TiledNetEntry kTiledNet[] = {
-    {256, 8, 1, k_tiled_net<256, 8, 1>}, {256, 8, 2, k_tiled_net<256, 8, 2>},
-    {256, 4, 1, k_tiled_net<256, 4, 1>}, {256, 4, 2, k_tiled_net<256, 4, 2>},
+    {256, 8, 1, false, k_tiled_net<256, 8, 1, false>}, {256, 8, 2, false, k_tiled_net<256, 8, 2, false>},
+    {256, 8, 1, true, k_tiled_net<256, 8, 1, true>},   {256, 8, 2, true, k_tiled_net<256, 8, 2, true>},
+    {256, 4, 1, false, k_tiled_net<256, 4, 1, false>}, {256, 4, 2, false, k_tiled_net<256, 4, 2, false>},
 };
 
 bool tiled_net_available(int nt, int iters) {
@@ -322,11 +406,12 @@ bool tiled_net_available(int nt, int iters) {
     return false;
 }
 
-hipError_t launch_tiled_net(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
+hipError_t launch_tiled_net(int nt, int iters, int op, bool regs, const void* in, void* out, const PassTables& tab,
                             const NetColumns& cols, uint32_t ntiles, uint32_t grid, hipStream_t stream) {
     if (tab.d < 1) return hipErrorInvalidValue;
+    if (regs && (cols.ngroups == 0 || tab.d != 13)) return hipErrorInvalidValue;
     for (const auto& e : kTiledNet) {
-        if (e.nt != nt || e.iters != iters || e.op != op) continue;
+        if (e.nt != nt || e.iters != iters || e.op != op || e.regs != regs) continue;
         if (grid == 0 || grid > ntiles) grid = ntiles;
         hipLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab, cols, ntiles,
                            0u);

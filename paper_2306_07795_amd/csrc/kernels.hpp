@@ -31,7 +31,7 @@ hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, voi
 // each staged tile in LDS before writing it (op 1: int32 order, 2: uint32).
 // Shapes (nt, iters) = (256, 8) and (256, 4).
 bool tiled_net_available(int nt, int iters);
-hipError_t launch_tiled_net(int nt, int iters, int op, const void* in, void* out, const PassTables& tab,
+hipError_t launch_tiled_net(int nt, int iters, int op, bool regs, const void* in, void* out, const PassTables& tab,
                             const NetColumns& cols, uint32_t ntiles, uint32_t grid, hipStream_t stream);
 
 // One sorting-network column in place at the keys' own positions: the pair k

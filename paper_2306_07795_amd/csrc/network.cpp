@@ -21,6 +21,7 @@
 // Q.(2k + 1) with Q = (M_s ... M_0)^-1), without the permutations.
 #include <algorithm>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -143,6 +144,11 @@ int run_direct(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
 // reads and writes in runs of 2^6 keys (256 bytes), so that every pass holds
 // at least one column (6 + 6 + 1 <= 13).
 constexpr int kNetThreads = 256, kNetIters = 8, kNetRunIn = 6, kNetRunOut = 6;
+// Fewest columns of a pass that runs them in register groups (measured on
+// 2^16..2^26 keys): the register kernel holds fewer work-groups per CU, which
+// costs a memory-bound pass more than it saves unless the pass has many
+// columns; while the keys fit the caches, a few columns suffice.
+uint32_t net_reg_min_cols(size_t bytes) { return bytes <= ((size_t)16 << 20) ? 4 : 16; }
 
 struct NetPass {
     PassPlan plan;
@@ -200,6 +206,60 @@ int column_tables(const PassTables& tab, uint64_t u, uint64_t g, NetCol* out) {
     return BMMC_OK;
 }
 
+// Register groups of a pass whose tile is a full 2^13 slots for 256 threads
+// (32 slots a thread): consecutive columns whose pair vectors f are among at
+// most kNetRegBits independent slot vectors form one group; its basis is
+// completed with unit vectors (lowest bits first) to kNetRegBits, then to a
+// basis of the slot space by 8 unit vectors for the thread bits.  Leaves
+// ngroups = 0 (the LDS path) for smaller tiles or more than kMaxNetGroups.
+void register_groups(uint32_t d, NetColumns* C) {
+    C->ngroups = 0;
+    if (d != 13 || C->count == 0) return;
+    const int kThreadBits = 8;
+    uint32_t ng = 0;
+    for (uint32_t i = 0; i < C->count;) {
+        if (ng == (uint32_t)kMaxNetGroups) {
+            C->ngroups = 0;
+            return;
+        }
+        NetGroup& G = C->grp[ng];
+        Basis sb;
+        int ns = 0;
+        uint32_t j = i;
+        for (; j < C->count; j++) {
+            const uint32_t f = C->col[j].f;
+            int k = 0;
+            while (k < ns && G.S[k] != f) k++;
+            if (k < ns) continue;  // already a basis vector
+            if (ns == kNetRegBits || !sb.insert(f)) break;
+            G.S[ns++] = f;
+        }
+        for (uint32_t b = 0; b < d && ns < kNetRegBits; b++)
+            if (sb.insert(1u << b)) G.S[ns++] = 1u << b;
+        G.cpos = 0;
+        int nc = 0;
+        for (uint32_t b = 0; b < d && nc < kThreadBits; b++)
+            if (sb.insert(1u << b)) G.cpos |= b << (4 * nc++);
+        if (ns != kNetRegBits || nc != kThreadBits) {  // cannot happen for d = 13
+            C->ngroups = 0;
+            return;
+        }
+        G.first = i;
+        G.last = j;
+        for (uint32_t c = i; c < j; c++) {
+            NetCol& col = C->col[c];
+            uint32_t idx = 0;
+            while (G.S[idx] != col.f) idx++;
+            uint32_t q = 0;
+            for (int k = 0; k < kNetRegBits; k++) q |= (uint32_t)(__builtin_popcount(col.beta & G.S[k]) & 1) << k;
+            col.rg = idx | (q << 3);
+        }
+        ng++;
+        i = j;
+    }
+    C->ngroups = ng;
+}
+
 int build_net_pass(const BitMat& T, const std::vector<uint64_t>& us, const std::vector<uint64_t>& gs,
                    uint64_t seed, NetPass* np) {
     const KernelShape ks = net_shape();
@@ -211,6 +271,7 @@ int build_net_pass(const BitMat& T, const std::vector<uint64_t>& us, const std::
         st = column_tables(np->plan.tab, us[i], gs[i], &np->cols.col[i]);
         if (st != BMMC_OK) return st;
     }
+    register_groups(np->plan.tab.d, &np->cols);
     return BMMC_OK;
 }
 
@@ -297,10 +358,14 @@ int run_passes(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
         void* dst = ((last - k) % 2 == 0) ? out : mid;
         const NetPass& np = (*passes)[k];
         const PassTables& tab = np.plan.tab;
-        snprintf(name, sizeof(name), "k_tiled_net<%d,%d,%d>", kNetThreads, kNetIters, op);
+        // register groups for passes with many columns; passes with few
+        // keep the LDS kernel, whose lower register use leaves more
+        // work-groups resident to hide the memory latency
+        const bool regs = np.cols.ngroups > 0 && np.cols.count >= net_reg_min_cols(bytes);
+        snprintf(name, sizeof(name), "k_tiled_net<%d,%d,%d,%d>", kNetThreads, kNetIters, op, regs ? 1 : 0);
         LaunchScope ls(ds, stream, name, 2.0 * bytes);
         hipError_t e =
-            launch_tiled_net(kNetThreads, kNetIters, op, src, dst, tab, np.cols, 1u << tab.ntb, 0, stream);
+            launch_tiled_net(kNetThreads, kNetIters, op, regs, src, dst, tab, np.cols, 1u << tab.ntb, 0, stream);
         if (e != hipSuccess) return hip_fail(e, "sorting-network pass launch");
         src = dst;
     }
@@ -311,7 +376,7 @@ int run_passes(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
 // the read phase by X and F, the columns by f, beta and g, the write phase by
 // Y and G, each 16-byte vector addressed as the kernel addresses it (the
 // vector index from the coordinates above the element bits).
-void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* dst) {
+int emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* dst) {
     const PassTables& P = np.plan.tab;
     const uint32_t d = P.d, slots = 1u << d;
     const uint32_t lv = d < 2 ? d : 2, em = (1u << lv) - 1u;  // 4-byte keys: 4 per vector
@@ -333,19 +398,62 @@ void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* 
             const uint32_t x = r ^ lin(P.X, v & ~em);
             lds[lin(P.F, v)] = src[(x & ~em) | (v & em)];
         }
-        for (uint32_t i = 0; i < np.cols.count; i++) {
-            const NetCol& c = np.cols.col[i];
-            const uint32_t p = __builtin_ctz(c.f), lo = (1u << p) - 1u;
-            const uint32_t alpha = __builtin_popcount(c.g & r) & 1u;
-            for (uint32_t k = 0; k < slots / 2; k++) {
-                const uint32_t s0 = ((k & ~lo) << 1) | (k & lo), s1 = s0 ^ c.f;
-                const uint32_t a = lds[s0], b = lds[s1];
-                const uint32_t hi0 = alpha ^ (__builtin_popcount(c.beta & s0) & 1u);
-                const bool gt = op == 1 ? (int32_t)a > (int32_t)b : a > b;
-                if (gt != (hi0 != 0)) {
-                    lds[s0] = b;
-                    lds[s1] = a;
+        if (np.cols.ngroups == 0) {
+            for (uint32_t i = 0; i < np.cols.count; i++) {
+                const NetCol& c = np.cols.col[i];
+                const uint32_t p = __builtin_ctz(c.f), lo = (1u << p) - 1u;
+                const uint32_t alpha = __builtin_popcount(c.g & r) & 1u;
+                for (uint32_t k = 0; k < slots / 2; k++) {
+                    const uint32_t s0 = ((k & ~lo) << 1) | (k & lo), s1 = s0 ^ c.f;
+                    const uint32_t a = lds[s0], b = lds[s1];
+                    const uint32_t hi0 = alpha ^ (__builtin_popcount(c.beta & s0) & 1u);
+                    const bool gt = op == 1 ? (int32_t)a > (int32_t)b : a > b;
+                    if (gt != (hi0 != 0)) {
+                        lds[s0] = b;
+                        lds[s1] = a;
+                    }
                 }
+            }
+        } else {
+            // the register groups as the kernel runs them: each of the 256
+            // threads loads its 32 slots, runs the group's columns on them,
+            // stores them back
+            for (uint32_t gi = 0; gi < np.cols.ngroups; gi++) {
+                const NetGroup& G = np.cols.grp[gi];
+                std::vector<uint32_t> next(lds);
+                std::vector<int> seen(slots, 0);
+                for (uint32_t t = 0; t < 256; t++) {
+                    uint32_t base = 0;
+                    for (int b = 0; b < 8; b++)
+                        if ((t >> b) & 1u) base |= 1u << ((G.cpos >> (4 * b)) & 15u);
+                    uint32_t slot[32], reg[32];
+                    for (uint32_t j = 0; j < 32; j++) {
+                        slot[j] = base;
+                        for (int k = 0; k < kNetRegBits; k++)
+                            if ((j >> k) & 1u) slot[j] ^= G.S[k];
+                        reg[j] = lds[slot[j]];
+                        seen[slot[j]]++;
+                    }
+                    for (uint32_t i = G.first; i < G.last; i++) {
+                        const NetCol& c = np.cols.col[i];
+                        const uint32_t idx = c.rg & 7u, q = c.rg >> 3;
+                        const uint32_t d0 = (__builtin_popcount(c.g & r) ^ __builtin_popcount(c.beta & base)) & 1u;
+                        for (uint32_t jl = 0; jl < 32; jl++) {
+                            if ((jl >> idx) & 1u) continue;
+                            const uint32_t jh = jl | (1u << idx);
+                            const uint32_t x = reg[jl], y = reg[jh];
+                            const bool lt = op == 1 ? (int32_t)x < (int32_t)y : x < y;
+                            const uint32_t mn = lt ? x : y, mx = lt ? y : x;
+                            const bool dir = (d0 ^ (__builtin_popcount(q & jl) & 1u)) != 0;
+                            reg[jl] = dir ? mx : mn;
+                            reg[jh] = dir ? mn : mx;
+                        }
+                    }
+                    for (uint32_t j = 0; j < 32; j++) next[slot[j]] = reg[j];
+                }
+                for (uint32_t v = 0; v < slots; v++)
+                    if (seen[v] != 1) return BMMC_ERR_INTERNAL;  // every slot in exactly one thread's registers
+                lds.swap(next);
             }
         }
         for (uint32_t u = 0; u < slots; u++) {
@@ -353,6 +461,7 @@ void emulate_net_pass(const NetPass& np, int op, const uint32_t* src, uint32_t* 
             dst[(y & ~em) | (u & em)] = lds[gx ^ lin(P.G, u)];
         }
     }
+    return BMMC_OK;
 }
 
 }  // namespace
@@ -389,7 +498,8 @@ extern "C" int bmmc_sortnet_emulate(const void* in, void* out, int n, int key_ty
     const size_t count = (size_t)1 << n;
     std::vector<uint32_t> a((const uint32_t*)in, (const uint32_t*)in + count), b(count);
     for (const NetPass& np : *passes) {
-        emulate_net_pass(np, key_type == BMMC_KEY_I32 ? 1 : 2, a.data(), b.data());
+        rc = emulate_net_pass(np, key_type == BMMC_KEY_I32 ? 1 : 2, a.data(), b.data());
+        if (rc != BMMC_OK) return set_error(rc, "register groups of a pass do not cover its tile");
         a.swap(b);
     }
     std::memcpy(out, a.data(), count * 4);

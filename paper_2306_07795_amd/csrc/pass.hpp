@@ -60,11 +60,30 @@ struct BatchItem {
 constexpr int kMaxNetCols = 96;
 struct NetCol {
     uint32_t f, beta, g;
+    uint32_t rg;  // register groups: index of f in its group's basis (bits 0-2), q (bits 3-7)
+};
+// Register groups (full 2^13-slot tiles of 256 threads): a run of columns
+// whose pair vectors are among kNetRegBits independent slot vectors S[0..4]
+// is done in registers.  Thread t holds the 32 slots base(t) XOR S(j),
+// j in [0, 32), where base(t) sets slot bit cpos[i] for each set bit i of t
+// (the unit vectors cpos complete S to a basis of the slot space).  For a
+// column with f = S[idx], the pair (j, j | 1 << idx) keeps the smaller key at
+// j exactly when parity(g & r) XOR parity(beta & base(t)) XOR parity(q & j)
+// is 0, q_k = parity(beta & S[k]).  One LDS round trip and one barrier per
+// group instead of one barrier per column.
+constexpr int kNetRegBits = 5;
+constexpr int kMaxNetGroups = 32;
+struct NetGroup {
+    uint32_t S[kNetRegBits];
+    uint32_t cpos;            // 8 slot-bit positions, 4 bits each, for thread bits 0..7
+    uint32_t first, last;     // columns [first, last)
 };
 struct NetColumns {
     uint32_t count;
-    uint32_t pad_[3];
+    uint32_t ngroups;  // 0: every column through LDS, one barrier each
+    uint32_t pad_[2];
     NetCol col[kMaxNetCols];
+    NetGroup grp[kMaxNetGroups];
 };
 
 // Per-pass device descriptor for the batched kernel.
