@@ -6,6 +6,7 @@
 // once XOR a compile-time-selected per-iteration part, so the per-element cost
 // is one XOR and one shift whatever the matrix.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -124,12 +125,18 @@ struct TileCtx {
         }
     }
 
-    // Read phase, LDS part: each element to its swizzled slot F(v).
+    // Read phase, LDS part: each element to its swizzled slot F(v).  With
+    // RECOMPUTE the slots are recomputed for every tile (a few XORs) rather
+    // than kept in registers across tiles, which frees registers for a
+    // register-hungry mid step; the empty asm hides that ftl equals ft.
+    template <bool RECOMPUTE>
     __device__ __forceinline__ void to_lds(const PassTables& P, E* lds, uint32_t tid, const Vec16<W>* buf) const {
+        uint32_t ftl = ft;
+        if constexpr (RECOMPUTE) asm volatile("" : "+v"(ftl));
 #pragma unroll
         for (int it = 0; it < ITERS; it++) {
             if ((uint32_t)(it * NT) + tid < vlim) {
-                const uint32_t f = ft ^ lin_const<LV + LT, LI>(P.F, it);
+                const uint32_t f = ftl ^ lin_const<LV + LT, LI>(P.F, it);
 #pragma unroll
                 for (int e = 0; e < VEC; e++) lds[f ^ lin_const<0, LV>(P.F, e)] = buf[it].e[e];
             }
@@ -172,7 +179,7 @@ struct TileCtx {
         Parts cur = parts(P, tile);
         load(P, in, cur.r, tid, buf);
         for (;;) {
-            to_lds(P, lds, tid, buf);
+            to_lds<!std::is_same<Mid, NoMid>::value>(P, lds, tid, buf);
             __syncthreads();
             const uint32_t next = tile + step;
             const bool more = next < last;
