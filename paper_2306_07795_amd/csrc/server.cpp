@@ -332,6 +332,9 @@ void Server::dispatch_loop() {
                 }
                 if (st == BMMC_OK && hipEventRecord(s.done, s.stream) != hipSuccess) st = BMMC_ERR_HIP;
                 if (st != BMMC_OK) {
+                    // launches enqueued before the failure may still use the
+                    // requests' memory: let them end before it is freed
+                    (void)hipStreamSynchronize(s.stream);
                     for (Request* r : s.reqs) {
                         r->status = st;
                         r->state = kFailed;
@@ -375,6 +378,7 @@ extern "C" int64_t bmmc_server_now_ns(void) { return now_ns(); }
 extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out) {
     if (!opts || !handle_out) return set_error(BMMC_ERR_ARG, "opts/handle_out is NULL");
     if (opts->budget_bytes < (1 << 20)) return set_error(BMMC_ERR_ARG, "budget below 1 MiB");
+    if (opts->solo_log2 > 40) return set_error(BMMC_ERR_ARG, "solo_log2 = %d above 40", opts->solo_log2);
     int st;
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
@@ -382,7 +386,6 @@ extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** hand
     s->opt = *opts;
     if (s->opt.streams <= 0) s->opt.streams = 4;
     if (s->opt.streams > 16) s->opt.streams = 16;
-    if (s->opt.solo_log2 > 40) return set_error(BMMC_ERR_ARG, "solo_log2 = %d above 40", s->opt.solo_log2);
     s->solo_bytes = s->opt.solo_log2 < 0 ? 0 : (size_t)1 << (s->opt.solo_log2 == 0 ? 24 : s->opt.solo_log2);
     s->ds = ds;
     s->device = ds->device;
@@ -399,8 +402,13 @@ extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** hand
     s->buddy.init(top, 12);
     s->slots.resize(s->opt.streams);
     for (Slot& sl : s->slots) {
-        hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        hipError_t e2 = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e2 != hipSuccess) {
+            (void)hipGetLastError();
+            bmmc_server_destroy(s);
+            return set_error(BMMC_ERR_HIP, "server stream or event: %s", hipGetErrorString(e2));
+        }
         // the batch table of each stream made now: allocating it (device
         // memory, pinned staging) while serving would stall every stream
         const int st2 = reserve_batch_state(sl.stream, ds->device, 128, 8192);
