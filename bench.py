@@ -275,17 +275,31 @@ def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, reps=20):
 
 def other_matrices(x, y, n, w, copy_ms, stream, seeds=8, reps=10):
     """The library's default call on random matrices of seeds 0..seeds-1 (the
-    timed workload is seed 0): beyond the last-level cache how the accesses
-    meet the memory system varies from one matrix to another."""
+    timed workload is seed 0), then the same after tuning each matrix:
+    beyond the last-level cache how the accesses meet the memory system
+    varies from one matrix to another."""
     from paper_2306_07795_amd import binding as B
     from synth import gen
-    pct = []
+    pct, per = [], []
     for seed in range(seeds):
         rows, c = gen.random_bmmc(n, seed)
         ms = timed(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream)
         pct.append(100.0 * copy_ms / ms)
-    return {"seeds": f"0-{seeds - 1}", "pct_of_device_copy": [round(p, 1) for p in pct],
-            "mean": round(sum(pct) / len(pct), 1), "min": round(min(pct), 1), "max": round(max(pct), 1)}
+    # the same calls after bmmc_autotune_matrix has tuned each matrix
+    # (before the timed calls; the settings are dropped afterwards)
+    try:
+        for seed in range(seeds):
+            rows, c = gen.random_bmmc(n, seed)
+            B.bmmc_autotune_matrix(x, y, n, rows, c, w, stream, 3)
+            ms = timed(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream)
+            per.append(100.0 * copy_ms / ms)
+    finally:
+        B.bmmc_tune_clear_matrices()
+
+    def summary(v):
+        return {"pct_of_device_copy": [round(p, 1) for p in v], "mean": round(sum(v) / len(v), 1),
+                "min": round(min(v), 1), "max": round(max(v), 1)}
+    return {"seeds": f"0-{seeds - 1}", **summary(pct), "tuned_per_matrix": summary(per)}
 
 
 def torch_sync():

@@ -376,11 +376,29 @@ int bmmc_batch_destroy(void* handle);
 int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
                   bmmc_options_t* best_out, double* best_ms);
 
-/* The tuned options of `method` for this matrix's class: returns 1 and fills
+/* The tuned options of `method` for this matrix (BMMC_METHOD_AUTO only,
+   from bmmc_autotune_matrix) or else for its class: returns 1 and fills
    *opts_out when the cache holds an entry, else 0.  With BMMC_METHOD_AUTO
    these are the options a call without options uses (else the library
    defaults).  Host only.  Errors: _ARG, _RANGE. */
 int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows, bmmc_options_t* opts_out);
+
+/* Tune for one matrix (Section 2 permutation, BMMC_METHOD_AUTO): times, on
+   these buffers, the options a call would use now under every tile order,
+   then a few other tile shapes (4- and 8-byte elements), and keeps the
+   fastest for later bmmc_permute calls (and served requests planned as
+   single-array calls) with this A and n, for any c.  Beyond the last-level cache the best setting differs from one
+   random matrix to the next.  Runs the permutation some 100-300 times and
+   synchronizes `stream`; `out` ends up holding the permutation of `in`.
+   The settings are kept in memory only (at most 4096 matrices: with 4096
+   stored, all are dropped before the next is added).  in, out: device buffers of 2^n * elem_bytes,
+   16-byte aligned, not overlapping.  *best_ms (if not NULL) receives the
+   time of one call.  Errors: _ARG, _RANGE, _ALIAS, _SINGULAR, _NOMEM, _HIP. */
+int bmmc_autotune_matrix(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c, int elem_bytes,
+                         void* stream, int reps, bmmc_options_t* best_out, double* best_ms);
+
+/* Forget every setting bmmc_autotune_matrix stored.  Host only. */
+int bmmc_tune_clear_matrices(void);
 
 /* Time method, tile size, chunk size, queue order and persistent grid size
    of the batched kernel on this very batch, then tile orders for the best

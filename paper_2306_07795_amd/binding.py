@@ -130,6 +130,8 @@ def lib():
         "bmmc_profile_end": (_i32, [P(KernelStat), _i32]),
         "bmmc_autotune_batched": (_i32, [P(Desc), _i32, _vp, _i32, P(BatchOptions), P(_dbl)]),
         "bmmc_autotune": (_i32, [_i32, _i32, _i32, _vp, _i32, P(Options), P(_dbl)]),
+        "bmmc_autotune_matrix": (_i32, [_vp, _vp, _i32, P(_u64), _u64, _i32, _vp, _i32, P(Options), P(_dbl)]),
+        "bmmc_tune_clear_matrices": (_i32, []),
         "bmmc_tune_save": (_i32, [_c.c_char_p]),
         "bmmc_tune_lookup": (_i32, [_i32, _i32, _i32, P(_u64), P(Options)]),
         "bmmc_tune_lookup_batched": (_i32, [P(Desc), _i32, P(BatchOptions)]),
@@ -164,7 +166,7 @@ def exported_names():
         "bmmc_server_submit", "bmmc_server_poll", "bmmc_server_release", "bmmc_server_drain",
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
         "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes", "bmmc_tune_lookup_batched",
-        "bmmc_server_reset_stats",
+        "bmmc_server_reset_stats", "bmmc_autotune_matrix", "bmmc_tune_clear_matrices",
     ]
 
 
@@ -461,9 +463,23 @@ def bmmc_autotune(n: int, elem_bytes: int, method: int = METHOD_AUTO, stream=Non
     return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}, ms.value
 
 
+def bmmc_autotune_matrix(inp, out, n: int, A_rows, c: int, elem_bytes: int, stream=None, reps: int = 3):
+    """Time settings for this very matrix on these buffers; the best is kept
+    for later calls with this matrix.  Returns (options dict, ms per call)."""
+    o = Options()
+    ms = _dbl(0)
+    _check(lib().bmmc_autotune_matrix(_ptr(inp), _ptr(out), n, _rows(A_rows, n), c, elem_bytes, _stream(stream),
+                                      reps, _c.byref(o), _c.byref(ms)))
+    return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}, ms.value
+
+
+def bmmc_tune_clear_matrices():
+    _check(lib().bmmc_tune_clear_matrices())
+
+
 def bmmc_tune_lookup(n: int, elem_bytes: int, A_rows, method: int = METHOD_AUTO):
-    """The tuned options of `method` for this matrix's class (dict), or None
-    when nothing is tuned for it."""
+    """The tuned options of `method` for this matrix, else for its class
+    (dict), or None when nothing is tuned for it."""
     o = Options()
     r = lib().bmmc_tune_lookup(n, elem_bytes, method, _rows(A_rows, n), _c.byref(o))
     if r < 0:

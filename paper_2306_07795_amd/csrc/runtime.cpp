@@ -383,7 +383,9 @@ int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchAr
     bmmc_options_t o;
     std::memset(&o, 0, sizeof(o));
     o.method = method;
-    tuned_options(d.n, d.elem_bytes, method, matrix_class(d.A_rows, d.n), &o);  // else the defaults
+    // the options tuned for this matrix, else for its class, else the defaults
+    if (!(method == BMMC_METHOD_AUTO && matrix_options(d.n, d.elem_bytes, d.A_rows, &o)))
+        tuned_options(d.n, d.elem_bytes, method, matrix_class(d.A_rows, d.n), &o);
     const bmmc_options_t eff = effective_options(ds, d.n, d.elem_bytes, &o);
     const int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, plan_options(&eff, d.elem_bytes), &out->plan);
     if (st != BMMC_OK) return st;
@@ -502,7 +504,9 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     bmmc_options_t tuned;
-    if (!opts && tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned)) opts = &tuned;
+    if (!opts && (matrix_options(n, elem_bytes, A_rows, &tuned) ||
+                  tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned)))
+        opts = &tuned;
     const bmmc_options_t eff = effective_options(ds, n, elem_bytes, opts);
     opts = &eff;
     PlanOptions po = plan_options(opts, elem_bytes);

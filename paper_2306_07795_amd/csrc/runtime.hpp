@@ -127,6 +127,8 @@ void release_batch_state(hipStream_t stream, int device);
 // width (bit permutations among them), else 0.
 int matrix_class(const uint64_t* rows, int n);
 bool tuned_options(int n, int w, int method, int cls, bmmc_options_t* out);
+// The options bmmc_autotune_matrix stored for this matrix, if any.
+bool matrix_options(int n, int w, const uint64_t* rows, bmmc_options_t* out);
 bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out);
 
 }  // namespace bmmc

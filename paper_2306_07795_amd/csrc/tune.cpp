@@ -4,7 +4,10 @@
 // two passes), class 1: tiled matrices such as bit permutations -- and per
 // batch signature for batched launches.  The cache can be saved to and loaded
 // from a JSON-lines file; BMMC_TUNE_CACHE names a file loaded on first use.
+// Options tuned for one matrix (bmmc_autotune_matrix) are kept in memory
+// only and take precedence over its class's.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <dlfcn.h>
 
@@ -29,7 +32,21 @@ struct TuneCache {
     bool loaded = false;
     std::map<std::tuple<int, int, int, int>, std::pair<bmmc_options_t, double>> plain;
     std::map<uint64_t, std::pair<bmmc_batch_options_t, double>> batch;
+    // per matrix: key {n, width, rows...}; `nmatrix` lets calls skip the
+    // lookup while the map is empty
+    std::map<std::vector<uint64_t>, bmmc_options_t> matrix;
+    std::atomic<size_t> nmatrix{0};
 };
+
+constexpr size_t kMaxMatrixEntries = 4096;
+
+std::vector<uint64_t> matrix_key(int n, int w, const uint64_t* rows) {
+    std::vector<uint64_t> k((size_t)n + 2);
+    k[0] = (uint64_t)n;
+    k[1] = (uint64_t)w;
+    for (int i = 0; i < n; i++) k[(size_t)i + 2] = rows[i] & low_mask(n);
+    return k;
+}
 
 TuneCache& cache() {
     static TuneCache c;
@@ -197,6 +214,17 @@ bool tuned_options(int n, int w, int method, int cls, bmmc_options_t* out) {
     return true;
 }
 
+bool matrix_options(int n, int w, const uint64_t* rows, bmmc_options_t* out) {
+    TuneCache& c = cache();
+    if (c.nmatrix.load(std::memory_order_relaxed) == 0 || n <= 0 || !rows) return false;
+    const std::vector<uint64_t> key = matrix_key(n, w, rows);
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.matrix.find(key);
+    if (it == c.matrix.end()) return false;
+    *out = it->second;
+    return true;
+}
+
 bool tuned_batch_options(uint64_t signature, bmmc_batch_options_t* out) {
     TuneCache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
@@ -215,6 +243,7 @@ extern "C" int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_
                                 bmmc_options_t* opts_out) {
     if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
     if (!opts_out || (n > 0 && !A_rows)) return set_error(BMMC_ERR_ARG, "NULL argument");
+    if (method == BMMC_METHOD_AUTO && matrix_options(n, elem_bytes, A_rows, opts_out)) return 1;
     return tuned_options(n, elem_bytes, method, matrix_class(A_rows, n), opts_out) ? 1 : 0;
 }
 
@@ -293,6 +322,31 @@ double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, 
     return total;
 }
 
+// The capture stream of the graph timing (null if none could be made), and
+// its release together with any scratch array the library made for it.
+hipStream_t make_capture_stream() {
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        cap = nullptr;
+        (void)hipGetLastError();
+    }
+    return cap;
+}
+
+void drop_capture_stream(DeviceState* ds, hipStream_t cap) {
+    if (!cap) return;
+    hipStreamSynchronize(cap);
+    {
+        std::lock_guard<std::mutex> lk(ds->mu);
+        auto it = ds->scratch.find(cap);
+        if (it != ds->scratch.end()) {
+            if (it->second.ptr) hipFree(it->second.ptr);
+            ds->scratch.erase(it);
+        }
+    }
+    hipStreamDestroy(cap);
+}
+
 // Two stages, each candidate timed on the matrices (`reps` runs each): first
 // tile shape, read/write runs, cache hints and method under two tile orders
 // and both grid kinds; then, for the six fastest of those, every tile order
@@ -309,11 +363,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
     const size_t kBases = 6, kFinal = 8;
     std::vector<std::pair<double, bmmc_options_t>> timed;
     Timer tm;
-    hipStream_t cap = nullptr;  // capture stream of the graph timing
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
-        cap = nullptr;
-        (void)hipGetLastError();
-    }
+    hipStream_t cap = make_capture_stream();
     const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
     // non-temporal stores (2) or loads and stores (3) beyond the last-level
     // cache, none (4) or stores only below it
@@ -420,18 +470,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
             *bo = timed[i].second;
         }
     if (*best < 1e30) *best /= (double)mats.size();
-    if (cap) {
-        hipStreamSynchronize(cap);
-        {
-            std::lock_guard<std::mutex> lk(ds->mu);
-            auto it = ds->scratch.find(cap);
-            if (it != ds->scratch.end()) {
-                if (it->second.ptr) hipFree(it->second.ptr);
-                ds->scratch.erase(it);
-            }
-        }
-        hipStreamDestroy(cap);
-    }
+    drop_capture_stream(ds, cap);
 }
 
 }  // namespace
@@ -582,5 +621,121 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     }
     if (best_out) *best_out = bo;
     if (best_ms) *best_ms = best;
+    return BMMC_OK;
+}
+
+// Time, on this matrix and these buffers, the options a call would use now
+// (the tuned options of its class, else the size defaults) under every tile
+// order, then a few other tile shapes under the tile orders that are usually
+// best; the fastest few again in three interleaved rounds; keep the winner
+// for later calls with this matrix.  Beyond the last-level cache the best
+// setting differs from one random matrix to the next (which memory units a
+// tile's runs and its neighbours' runs fall on depends on the matrix).
+extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint64_t* A_rows, uint64_t c,
+                                    int elem_bytes, void* stream_, int reps, bmmc_options_t* best_out,
+                                    double* best_ms) {
+    if (n < 1 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [1, %d]", n, BMMC_MAX_BITS);
+    if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
+        return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
+    if (!A_rows) return set_error(BMMC_ERR_ARG, "A_rows is NULL");
+    const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
+    int st = validate_buffers(in, out, bytes);
+    if (st != BMMC_OK) return st;
+    if (reps < 1) reps = 3;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    std::vector<TuneMatrix> mats(1);
+    for (int i = 0; i < n; i++) mats[0].rows[i] = A_rows[i];
+    mats[0].c = c;
+    // a singular or malformed matrix fails here, before any timing
+    st = bmmc_permute_ex(in, out, n, A_rows, c, elem_bytes, nullptr, stream);
+    if (st != BMMC_OK) return st;
+
+    bmmc_options_t base;
+    std::memset(&base, 0, sizeof(base));
+    tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &base);
+    base = effective_options(ds, n, elem_bytes, &base);
+    static const int kOutAdj[] = {0, 2, 4, 5, 6, 7, 8, 9, 10, 12, 15};
+    static const int kAltOutAdj[] = {4, 6, 7, 8, 10};
+    // (threads, vectors per thread, read-run bits, write-run bits) of 4-byte
+    // elements; 8-byte elements take one write-run bit less
+    static const int kAltShapes[][4] = {{1024, 4, 6, 8}, {1024, 4, 5, 9}, {512, 8, 6, 8}, {256, 8, 5, 8}, {512, 4, 5, 8}};
+    std::vector<bmmc_options_t> cands;
+    for (int k : kOutAdj) {
+        bmmc_options_t o = base;
+        o.tile_order = ((base.tile_order & 7) == 1 ? 1 : 4) + 16 * k;
+        cands.push_back(o);
+    }
+    {
+        bmmc_options_t o = base;
+        o.tile_order = 2;  // XOR-mixed tile selection
+        cands.push_back(o);
+    }
+    if ((elem_bytes == 4 || elem_bytes == 8) && base.method != BMMC_METHOD_TILED) {
+        for (const auto& sh : kAltShapes) {
+            const int b = sh[3] - (elem_bytes == 8 ? 1 : 0);
+            if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
+            if (sh[0] == base.threads && sh[1] == base.iters && sh[2] == base.run_in && b == base.run_out) continue;
+            for (int k : kAltOutAdj) {
+                bmmc_options_t o = base;
+                o.threads = sh[0];
+                o.iters = sh[1];
+                o.run_in = sh[2];
+                o.run_out = b;
+                o.t = sh[2] < b ? sh[2] : b;
+                o.tile_order = 4 + 16 * k;
+                if (base.grid > 0) o.grid = ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
+                cands.push_back(o);
+            }
+        }
+    }
+    Timer tm;
+    hipStream_t cap = make_capture_stream();
+    std::vector<std::pair<double, bmmc_options_t>> timed;
+    for (const bmmc_options_t& o : cands) {
+        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm);
+        if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
+    }
+    std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    const size_t keep = timed.size() < 4 ? timed.size() : 4;
+    std::vector<double> again(keep, 1e30);
+    for (int round = 0; round < 3; round++)
+        for (size_t i = 0; i < keep; i++) {
+            const double per_call = timed[i].first;
+            int r = (int)std::ceil(5.0 / (per_call > 1e-4 ? per_call : 1e-4));
+            r = std::max(reps * 2, std::min(r, 200));
+            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm);
+            if (t > 0 && t < again[i]) again[i] = t;
+        }
+    drop_capture_stream(ds, cap);
+    double best = 1e30;
+    bmmc_options_t bo;
+    std::memset(&bo, 0, sizeof(bo));
+    for (size_t i = 0; i < keep; i++)
+        if (again[i] < best) {
+            best = again[i];
+            bo = timed[i].second;
+        }
+    if (best >= 1e30) return set_error(BMMC_ERR_RANGE, "no candidate setting ran for n = %d, w = %d", n, elem_bytes);
+    {
+        TuneCache& tc = cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        if (tc.matrix.size() >= kMaxMatrixEntries) tc.matrix.clear();
+        tc.matrix[matrix_key(n, elem_bytes, A_rows)] = bo;
+        tc.nmatrix.store(tc.matrix.size(), std::memory_order_relaxed);
+    }
+    // `out` holds the permutation of `in` again (every timed call wrote it)
+    if (best_out) *best_out = bo;
+    if (best_ms) *best_ms = best;
+    return BMMC_OK;
+}
+
+// Forget every per-matrix setting.
+extern "C" int bmmc_tune_clear_matrices(void) {
+    TuneCache& tc = cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    tc.matrix.clear();
+    tc.nmatrix.store(0, std::memory_order_relaxed);
     return BMMC_OK;
 }

@@ -170,6 +170,46 @@ def test_autotune_batched_small():
     check_all(arrays)
 
 
+@pytest.mark.parametrize("n,w", [(20, 4), (23, 8)])
+def test_autotune_matrix_then_permute(n, w):
+    """Per-matrix tuning (graph-timed below 64 MiB, plainly from 64 MiB):
+    its output is the permutation, the setting is what later calls of this
+    matrix use, they stay bit-exact, and clearing falls back to the class."""
+    rows, c = gen.random_bmmc(n, 21)
+    a = gen.data(n, w, 21)
+    want = O.permute(a, n, rows, c)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    try:
+        opts, ms = B.bmmc_autotune_matrix(x, y, n, rows, c, w, G.stream(), 2)
+        G.sync()
+        assert ms > 0 and np.array_equal(G.to_host(y, a), want)
+        assert B.bmmc_tune_lookup(n, w, rows) == opts
+        y.zero_()
+        B.bmmc_permute(x, y, n, rows, c ^ 1, w, G.stream())  # same A, other c: same setting
+        G.sync()
+        assert np.array_equal(G.to_host(y, a), O.permute(a, n, rows, c ^ 1))
+    finally:
+        B.bmmc_tune_clear_matrices()
+    after = B.bmmc_tune_lookup(n, w, rows)
+    assert after is None or after == B.bmmc_tune_lookup(n, w, gen.random_bmmc(n, 22)[0])
+
+
+def test_autotune_matrix_errors():
+    n, w = 12, 4
+    a = gen.data(n, w, 3)
+    x, y = G.to_device(a), G.empty_like_bytes(a)
+    singular = [1] * n
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_autotune_matrix(x, y, n, singular, 0, w, G.stream(), 1)
+    assert e.value.status == -2
+    r3 = gen.random_bmmc(n, 3)[0]
+    with pytest.raises(B.BmmcError) as e:
+        B.bmmc_autotune_matrix(x, x, n, r3, 0, w, G.stream(), 1)
+    assert e.value.status == -4
+    # nothing stored for the matrix whose tuning failed: it gets its class's
+    assert B.bmmc_tune_lookup(n, w, r3) == B.bmmc_tune_lookup(n, w, gen.random_bmmc(n, 4)[0])
+
+
 # ------------------------------------------------------------------ server
 
 @pytest.mark.parametrize("solo_log2", [0, 16, -1])
