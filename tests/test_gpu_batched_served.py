@@ -170,7 +170,7 @@ def test_autotune_batched_small():
     check_all(arrays)
 
 
-@pytest.mark.parametrize("n,w", [(20, 4), (23, 8)])
+@pytest.mark.parametrize("n,w", [(3, 4), (13, 16), (20, 4), (23, 8)])
 def test_autotune_matrix_then_permute(n, w):
     """Per-matrix tuning (graph-timed below 64 MiB, plainly from 64 MiB):
     its output is the permutation, the setting is what later calls of this
