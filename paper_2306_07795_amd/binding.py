@@ -96,6 +96,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_07795_amd.build`")
+    # PyTorch ships its own copy of the HIP runtime.  Loaded after this
+    # library, it would be a second runtime in the process, and this
+    # library's would then find no device; loaded first, both share it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = _c.CDLL(LIB_PATH)
     P = _c.POINTER
     sig = {

@@ -30,8 +30,8 @@ struct BatchState {
     // one captured graph per (cache hints, tile iterations, second phase)
     // setting (batches of different sizes alternate between them), each for
     // one grid size
-    hipGraphExec_t exec[16] = {};
-    uint32_t exec_grid[16] = {};
+    hipGraphExec_t exec[32] = {};
+    uint32_t exec_grid[32] = {};
 };
 
 struct BatchRegistry {
@@ -146,7 +146,9 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int 
     return BMMC_OK;
 }
 
-int graph_slot(int hints, int iters, bool second) { return (hints & 3) | (iters == 8 ? 4 : 0) | (second ? 8 : 0); }
+int graph_slot(int hints, int size, bool second) {
+    return (hints & 3) | (size == 8 ? 4 : size == 16 ? 8 : 0) | (second ? 16 : 0);
+}
 
 int build_graph(BatchState* bs, uint32_t grid, int hints, int iters, bool second) {
     const int slot = graph_slot(hints, iters, second);
@@ -323,8 +325,8 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iter
     if (d.elem_bytes >= 4) {
         // the batched kernel's one shape
         po.shape = default_shape(d.elem_bytes);
-        po.shape.nt = batched_threads();
-        po.shape.iters = batched_iters(iters);
+        po.shape.nt = batched_threads(batched_size(iters));
+        po.shape.iters = batched_vectors(batched_size(iters));
         po.shape_given = true;
     }
     int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, po, &out->plan);
@@ -342,6 +344,15 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iter
     return BMMC_OK;
 }
 
+// Every array the persistent kernel runs was planned for its tile shape
+// (the tables address the tile's slots by that shape).
+int check_batch_shapes(const std::vector<BatchArray>& arrays, int size) {
+    for (const BatchArray& a : arrays)
+        if (!a.single && (a.plan->shape.nt != batched_threads(size) || a.plan->shape.iters != batched_vectors(size)))
+            return set_error(BMMC_ERR_INTERNAL, "array planned for another batched tile shape");
+    return BMMC_OK;
+}
+
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream) {
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
@@ -355,6 +366,8 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
             return set_error(BMMC_ERR_INTERNAL, "two-pass array without scratch");
         }
     }
+    st = check_batch_shapes(arrays, batched_size(o.iters));
+    if (st != BMMC_OK) return st;
     const std::vector<size_t> work = work_order(arrays, o.order);
     if (work.empty()) return BMMC_OK;
     size_t npasses, nitems;
@@ -382,7 +395,7 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     if (!bs->staged) hipEventCreateWithFlags(&bs->staged, hipEventDisableTiming);
     hipEventRecord(bs->staged, stream);
 
-    const int iters = batched_iters(o.iters);
+    const int iters = batched_size(o.iters);
     uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(iters));
     const uint32_t* range = (const uint32_t*)h;
     const bool second = range[2] > range[1];
@@ -437,7 +450,8 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
-    if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16)
+        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8 or 16");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
@@ -500,7 +514,8 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
-    if (o.iters != 0 && o.iters != 4 && o.iters != 8) return set_error(BMMC_ERR_ARG, "iters must be 0, 4 or 8");
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16)
+        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8 or 16");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
@@ -539,6 +554,8 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
             if (!pb->arrays[i].single && pb->arrays[i].plan->npass == 2)
                 pb->arrays[i].scratch = (uint8_t*)pb->scratch + offs[i];
     }
+    st = check_batch_shapes(pb->arrays, batched_size(o.iters));
+    if (st != BMMC_OK) return fail(st);
     const std::vector<size_t> work = work_order(pb->arrays, o.order);
     size_t npasses, nitems;
     table_counts(pb->arrays, work, chunk, &npasses, &nitems);
@@ -558,7 +575,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     }
     e = hipMemcpy(pb->table, image.data(), pb->L.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpy (batch table)"));
-    pb->iters = batched_iters(o.iters);
+    pb->iters = batched_size(o.iters);
     pb->grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(pb->iters));
     pb->hints = resolve_batch_hints(o, pb->moved);
     pb->use_graph = o.use_graph >= 0;

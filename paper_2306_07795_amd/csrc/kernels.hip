@@ -606,28 +606,26 @@ hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream) {
 // second passes, so every second pass reads a scratch array whose first pass
 // has completed, without any wait or device-wide fence inside a kernel.
 // Every width (4, 8 or 16 bytes; the host sends narrower elements through
-// the single-array kernels) uses the same tile buffer of 256 threads x ITERS
-// vectors x 16 bytes (ITERS = 4 or 8: 16 or 32 KiB).  Thread 0 fetches the
-// next item's index as soon as the current item starts, so the atomic's
-// latency overlaps the current item's tiles.
+// the single-array kernels) uses the same tile buffer of NT threads x ITERS
+// vectors x 16 bytes (256 x 4, 256 x 8 or 512 x 8: 16, 32 or 64 KiB).
+// Thread 0 fetches the next item's index as soon as the current item
+// starts, so the atomic's latency overlaps the current item's tiles.
 // ---------------------------------------------------------------------------
-constexpr int kBatchNT = 256;
-
-template <int W, int HINT, int ITERS>
+template <int W, int HINT, int NT, int ITERS>
 __device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, uint32_t t1,
                                             uint8_t* lds_bytes, uint32_t tid) {
-    using C = TileCtx<W, kBatchNT, ITERS, HINT>;
+    using C = TileCtx<W, NT, ITERS, HINT>;
     C ctx;
     ctx.init(bp.tab, tid);
     ctx.run_tiles(bp.tab, (const g_u32x4*)bp.in, (g_u32x4*)bp.out, (typename C::E*)lds_bytes, t0, t1, 1, tid);
 }
 
 // range[phase] .. range[phase + 1] are this launch's items.
-template <int HINT, int ITERS>
-__global__ void __launch_bounds__(kBatchNT)
+template <int HINT, int NT, int ITERS>
+__global__ void __launch_bounds__(NT)
 k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ items,
           const uint32_t* __restrict__ range, uint32_t phase, uint32_t* head) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kBatchNT * ITERS * 16];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[NT * ITERS * 16];
     __shared__ uint32_t s_next;
     const uint32_t tid = threadIdx.x;
     const uint32_t first = range[phase], last = range[phase + 1];
@@ -641,43 +639,48 @@ k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ it
         const BatchItem item = items[idx];
         const BatchPass& bp = passes[item.pass];
         switch (bp.w) {
-            case 4: batch_tiles<4, HINT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
-            case 8: batch_tiles<8, HINT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
-            default: batch_tiles<16, HINT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 4: batch_tiles<4, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 8: batch_tiles<8, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            default: batch_tiles<16, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
         }
         __syncthreads();  // s_next written by thread 0 is visible to all
     }
 }
 
 hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* range,
-                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, int iters, hipStream_t stream) {
-#define BMMC_BATCHED(H, I) \
-    hipLaunchKernelGGL((k_batched<H, I>), dim3(grid), dim3(kBatchNT), 0, stream, passes, items, range, phase, head)
-    if (iters == 8) {
-        switch (hints & 3) {
-            case 0: BMMC_BATCHED(0, 8); break;
-            case 1: BMMC_BATCHED(1, 8); break;
-            case 2: BMMC_BATCHED(2, 8); break;
-            default: BMMC_BATCHED(3, 8); break;
-        }
-    } else if (iters == 4) {
-        switch (hints & 3) {
-            case 0: BMMC_BATCHED(0, 4); break;
-            case 1: BMMC_BATCHED(1, 4); break;
-            case 2: BMMC_BATCHED(2, 4); break;
-            default: BMMC_BATCHED(3, 4); break;
-        }
+                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, int size, hipStream_t stream) {
+#define BMMC_BATCHED(H, NT, I) \
+    hipLaunchKernelGGL((k_batched<H, NT, I>), dim3(grid), dim3(NT), 0, stream, passes, items, range, phase, head)
+#define BMMC_BATCHED_H(NT, I)                  \
+    switch (hints & 3) {                        \
+        case 0: BMMC_BATCHED(0, NT, I); break; \
+        case 1: BMMC_BATCHED(1, NT, I); break; \
+        case 2: BMMC_BATCHED(2, NT, I); break; \
+        default: BMMC_BATCHED(3, NT, I); break; \
+    }
+    if (size == 16) {
+        BMMC_BATCHED_H(512, 8)
+    } else if (size == 8) {
+        BMMC_BATCHED_H(256, 8)
+    } else if (size == 4) {
+        BMMC_BATCHED_H(256, 4)
     } else {
         return hipErrorInvalidValue;
     }
+#undef BMMC_BATCHED_H
 #undef BMMC_BATCHED
     return hipGetLastError();
 }
 
-int batched_occupancy(int iters) {
+int batched_occupancy(int size) {
     int blocks = 0;
-    hipError_t e = iters == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 8>, kBatchNT, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 4>, kBatchNT, 0);
+    hipError_t e;
+    if (size == 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 512, 8>, 512, 0);
+    else if (size == 8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 256, 8>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 256, 4>, 256, 0);
     if (e != hipSuccess) blocks = 4;
     return blocks > 0 ? blocks : 1;
 }

@@ -56,14 +56,16 @@ hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stre
 // (device pointers; *head must be zero at launch) with tiles of 256 threads x
 // `iters` (4 or 8) 16-byte vectors.
 hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* range,
-                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, int iters, hipStream_t stream);
+                          uint32_t phase, uint32_t* head, uint32_t grid, int hints, int size, hipStream_t stream);
 // Resident work-groups per CU of the batched kernel / of a tiled kernel.
-int batched_occupancy(int iters);
+int batched_occupancy(int size);
 int tiled_occupancy(int w, int nt, int iters, int hints = 0);
-// Shape of the batched kernel's tile: 256 threads, 4 vectors per thread
-// unless the batch options ask for 8.
-inline int batched_threads() { return 256; }
-inline int batched_iters(int asked) { return asked == 8 ? 8 : 4; }
+// Shape of the batched kernel's tile by its size, the tile's 16-byte vectors
+// over 256 (the batch option `iters`): 4 (default) -> 256 threads x 4
+// vectors, 8 -> 256 x 8, 16 -> 512 x 8.
+inline int batched_size(int asked) { return asked == 8 || asked == 16 ? asked : 4; }
+inline int batched_threads(int size) { return size == 16 ? 512 : 256; }
+inline int batched_vectors(int size) { return size == 16 ? 8 : size; }
 
 // Clears `count` 32-bit words with a kernel (no memset nodes in graphs).
 hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream);
