@@ -152,7 +152,8 @@ typedef struct {
     int method;         /* bmmc_method for the arrays larger than a tile */
     int hints;          /* as bmmc_options_t.hints (0: non-temporal above 64 MiB moved) */
     int iters;          /* tile size in 256s of 16-byte vectors: 4 (default: 256 threads x 4
-                           vectors, 16 KiB), 8 (256 x 8, 32 KiB) or 16 (512 x 8, 64 KiB) */
+                           vectors, 16 KiB), 8 (256 x 8, 32 KiB), 16 (512 x 8, 64 KiB) or
+                           32 (1024 x 8, 128 KiB) */
     int tile_order;     /* as bmmc_options_t.tile_order, bits 1, 2 and 16*k (0: plain order) */
 } bmmc_batch_options_t;
 

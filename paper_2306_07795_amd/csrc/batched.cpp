@@ -147,7 +147,7 @@ int capture_graph_at(uint8_t* d, const Layout& L, uint32_t grid, int hints, int 
 }
 
 int graph_slot(int hints, int size, bool second) {
-    return (hints & 3) | (size == 8 ? 4 : size == 16 ? 8 : 0) | (second ? 16 : 0);
+    return (hints & 3) | (size == 8 ? 4 : size == 16 ? 8 : size == 32 ? 12 : 0) | (second ? 16 : 0);
 }
 
 int build_graph(BatchState* bs, uint32_t grid, int hints, int iters, bool second) {
@@ -450,8 +450,8 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
-    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16)
-        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8 or 16");
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
+        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
@@ -514,8 +514,8 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else tuned_batch_options(batch_signature(descs, count), &o);
-    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16)
-        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8 or 16");
+    if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
+        return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;

@@ -607,7 +607,8 @@ hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream) {
 // has completed, without any wait or device-wide fence inside a kernel.
 // Every width (4, 8 or 16 bytes; the host sends narrower elements through
 // the single-array kernels) uses the same tile buffer of NT threads x ITERS
-// vectors x 16 bytes (256 x 4, 256 x 8 or 512 x 8: 16, 32 or 64 KiB).
+// vectors x 16 bytes (256 x 4, 256 x 8, 512 x 8 or 1024 x 8: 16, 32, 64 or
+// 128 KiB).
 // Thread 0 fetches the next item's index as soon as the current item
 // starts, so the atomic's latency overlaps the current item's tiles.
 // ---------------------------------------------------------------------------
@@ -658,7 +659,9 @@ hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const
         case 2: BMMC_BATCHED(2, NT, I); break; \
         default: BMMC_BATCHED(3, NT, I); break; \
     }
-    if (size == 16) {
+    if (size == 32) {
+        BMMC_BATCHED_H(1024, 8)
+    } else if (size == 16) {
         BMMC_BATCHED_H(512, 8)
     } else if (size == 8) {
         BMMC_BATCHED_H(256, 8)
@@ -675,7 +678,9 @@ hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const
 int batched_occupancy(int size) {
     int blocks = 0;
     hipError_t e;
-    if (size == 16)
+    if (size == 32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 1024, 8>, 1024, 0);
+    else if (size == 16)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 512, 8>, 512, 0);
     else if (size == 8)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<0, 256, 8>, 256, 0);

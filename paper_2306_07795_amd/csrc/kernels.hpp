@@ -62,10 +62,10 @@ int batched_occupancy(int size);
 int tiled_occupancy(int w, int nt, int iters, int hints = 0);
 // Shape of the batched kernel's tile by its size, the tile's 16-byte vectors
 // over 256 (the batch option `iters`): 4 (default) -> 256 threads x 4
-// vectors, 8 -> 256 x 8, 16 -> 512 x 8.
-inline int batched_size(int asked) { return asked == 8 || asked == 16 ? asked : 4; }
-inline int batched_threads(int size) { return size == 16 ? 512 : 256; }
-inline int batched_vectors(int size) { return size == 16 ? 8 : size; }
+// vectors, 8 -> 256 x 8, 16 -> 512 x 8, 32 -> 1024 x 8.
+inline int batched_size(int asked) { return asked == 8 || asked == 16 || asked == 32 ? asked : 4; }
+inline int batched_threads(int size) { return size == 32 ? 1024 : size == 16 ? 512 : 256; }
+inline int batched_vectors(int size) { return size >= 16 ? 8 : size; }
 
 // Clears `count` 32-bit words with a kernel (no memset nodes in graphs).
 hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream);

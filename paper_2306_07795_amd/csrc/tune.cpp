@@ -574,7 +574,7 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
         return BMMC_OK;
     };
     for (int method : {BMMC_METHOD_AUTO, BMMC_METHOD_TILED}) {
-        for (int iters : {4, 8, 16}) {
+        for (int iters : {4, 8, 16, 32}) {
             const int occ = batched_occupancy(iters);
             for (int chunk : kChunks) {
                 for (int order = 0; order < 2; order++) {

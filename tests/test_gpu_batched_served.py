@@ -54,7 +54,7 @@ def test_batched_mixed_sizes_and_widths(order, use_graph, hints, method):
 
 
 @pytest.mark.parametrize("tile_order", [0, 2, 4 + 16 * 7])
-@pytest.mark.parametrize("iters", [4, 8, 16])
+@pytest.mark.parametrize("iters", [4, 8, 16, 32])
 @pytest.mark.parametrize("chunk", [1, 4, 16])
 def test_batched_chunks_and_grid(chunk, iters, tile_order):
     sizes = gen.batched_sizes(40, chunk, 10, 20)
@@ -89,7 +89,7 @@ def test_graph_replays_with_fresh_data():
         check_all(arrays)
 
 
-@pytest.mark.parametrize("iters", [4, 8, 16])
+@pytest.mark.parametrize("iters", [4, 8, 16, 32])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 def test_batch_of_1024_like_the_workload(method, iters):
     """1024 arrays, n uniform in [10, 22], int32, each with its own A and c
@@ -295,7 +295,7 @@ def test_server_budget_admission_and_caller_outputs(method):
         B.bmmc_server_destroy(srv)
 
 
-@pytest.mark.parametrize("iters", [4, 8, 16])
+@pytest.mark.parametrize("iters", [4, 8, 16, 32])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 def test_prepared_batch_replays(method, iters):
     """A resident batch (plans, table, scratch and graph made once) replayed

@@ -80,8 +80,8 @@ def test_batched_validation_rejects_overlaps():
     for items in (ok, shared_input):
         arr, keep, k = B.make_descs(items)
         assert B.lib().bmmc_permute_batched(arr, k, None) in (0, -6)
-    # tile sizes other than 4, 8 or 16 are refused before any device work
-    for bad in (2, 12, 32):
+    # tile sizes other than 4, 8, 16 or 32 are refused before any device work
+    for bad in (2, 12, 64):
         with pytest.raises(B.BmmcError) as e:
             B.bmmc_permute_batched(ok, None, {"iters": bad})
         assert e.value.status == -1
