@@ -342,7 +342,10 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
    same stream.  descs is
    a host array of `count` descriptors; every in/out pair obeys the rules
    above and no out may overlap another array's in or out.  Scratch, the
-   device descriptor table and the graph are owned by the library.
+   device descriptor table and the graph are owned by the library.  Options
+   come from the tuning cache for this histogram of (n, width); without an
+   entry, batches moving 256 MiB or more take 128 KiB tiles, one per work
+   item, smaller ones the defaults of bmmc_batch_options_t.
    Errors: as bmmc_permute, reported for the first bad descriptor. */
 int bmmc_permute_batched(const bmmc_desc_t* descs, int count, void* stream);
 int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count,

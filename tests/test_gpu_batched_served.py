@@ -65,6 +65,18 @@ def test_batched_chunks_and_grid(chunk, iters, tile_order):
     check_all(arrays)
 
 
+def test_batched_untuned_large_batch_defaults():
+    """A batch of 512 MiB with no tuned entry and no options takes the
+    128 KiB tiles (one per item); every array still bit-exact."""
+    sizes = [22] * 8 + [21] * 8 + [23] * 8
+    widths = [4] * 8 + [8] * 8 + [4] * 8
+    arrays = make_batch(sizes, widths, 17)
+    assert B.bmmc_tune_lookup_batched(items(arrays)) is None
+    B.bmmc_permute_batched(items(arrays), G.stream())
+    G.sync()
+    check_all(arrays)
+
+
 def test_batched_onepass_method():
     sizes = gen.batched_sizes(32, 9, 10, 21)
     arrays = make_batch(sizes, [4, 8] * 16, 9)
