@@ -356,8 +356,10 @@ void Server::dispatch_loop() {
             }
         }
         if (!progress) {
-            // Sleep until new work arrives or briefly, to poll the streams.
-            int64_t wait_ns = 20000;
+            // Sleep until new work arrives or briefly, to poll the streams:
+            // every 5 us (at 20k requests/s, 20 us between polls put about
+            // 10 us on the median latency, measured).
+            int64_t wait_ns = 5000;
             if (!future.empty()) wait_ns = std::min<int64_t>(wait_ns, std::max<int64_t>(0, future.top()->arrival_ns - now_ns()));
             bool any_busy = false;
             for (Slot& s : slots) any_busy |= s.busy;
