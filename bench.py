@@ -388,7 +388,8 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     }
 
 
-def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0, solo_log2=0):
+def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0, solo_log2=0,
+                 streams=4):
     """Open-loop Poisson arrivals at `rate` requests/s for `seconds`: n uniform
     in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs resident in
     a pool per (n, width); outputs and scratch from the server's HBM budget.
@@ -406,7 +407,7 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0
     for r in reqs:
         mats[r["id"]] = gen.random_bmmc(r["n"], r["seed"])
     torch.cuda.synchronize()
-    srv = B.bmmc_server_create(budget, streams=4, own_outputs=2, use_graph=use_graph, direct_max=direct_max,
+    srv = B.bmmc_server_create(budget, streams=streams, own_outputs=2, use_graph=use_graph, direct_max=direct_max,
                                solo_log2=solo_log2)
     try:
         # warm-up: a quarter second of the same stream (other matrices), then
