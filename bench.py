@@ -89,27 +89,92 @@ def gbps(nbytes, ms):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(a, n, rows, c, budget_s=12.0):
-    """The oracle, as is, on this host's cores: repeats of the full workload
-    until about budget_s seconds have passed (at least one), then one run on
-    a single thread."""
+def progress(msg):
+    """One line on stderr as each part of a run finishes."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+# Cache state of the headline: before every timed call, a copy of
+# FLUSH_BYTES between two other buffers (outside the timed interval) leaves
+# the L2 caches and the 256 MB last-level cache holding another array's
+# lines, many of them dirty -- the state of a call that follows unrelated
+# work.  The library's autotuner times calls of 64 MiB and more the same way.
+FLUSH_BYTES = 512 << 20
+FLUSH_KERNEL = "k_copy<1,0>"
+
+
+class Flusher:
+    def __init__(self, device):
+        import torch
+        self.a = torch.full((FLUSH_BYTES,), 0x3C, dtype=torch.uint8, device=device)
+        self.b = torch.empty_like(self.a)
+
+    def __call__(self, stream):
+        from paper_2306_07795_amd import binding as B
+        B.bmmc_copy_ex(self.a, self.b, FLUSH_BYTES, 1, 0, stream)
+
+
+def flushed_times(fn, reps, warmup, stream, flush):
+    """Per-call times (ms) of fn(), each call right after a cache flush; HIP
+    events on the stream around the call only."""
+    import torch
+    for _ in range(warmup):
+        flush(stream)
+        fn()
+    evs = []
+    for _ in range(reps):
+        flush(stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def mean(v):
+    return sum(v) / len(v)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(a, n, rows, c, run_s=4.0, runs=3):
+    """The oracle, as is, on this host's cores: `runs` runs, each repeating
+    the full workload until about run_s seconds have passed (at least once);
+    the median run's rate is the value.  Then one run on a single thread."""
     from oracle import oracle as orc
     cores = orc.threads(0)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        orc.permute(a, n, rows, c, 0)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s or reps >= 200:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    # and once on a single thread
+    rates, reps_per_run = [], []
+    for _ in range(runs):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            orc.permute(a, n, rows, c, 0)
+            reps += 1
+            if time.perf_counter() - t0 > run_s or reps >= 200:
+                break
+        dt = (time.perf_counter() - t0) / reps
+        rates.append(2.0 * a.nbytes / dt / 1e9)
+        reps_per_run.append(reps)
+    med = sorted(rates)[len(rates) // 2]
     t1 = time.perf_counter()
     orc.permute(a, n, rows, c, 1)
     dt1 = time.perf_counter() - t1
-    return {"value": round(2.0 * a.nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
-            "kind": "oracle", "value_1_thread": round(2.0 * a.nbytes / dt1 / 1e9, 3),
-            "sample": f"the full workload (2^{n} elements), {reps} repetition(s) of {dt:.2f} s on "
-                      f"{cores} threads, then one of {dt1:.2f} s on 1 thread"}
+    return {"value": round(med, 3), "unit": "GB/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(), "runs_GBps": [round(r, 3) for r in rates],
+            "value_1_thread": round(2.0 * a.nbytes / dt1 / 1e9, 3),
+            "sample": f"the full workload (2^{n} elements), median of {runs} runs of about {run_s:.0f} s "
+                      f"({'/'.join(map(str, reps_per_run))} repetitions) on {cores} threads, then one of "
+                      f"{dt1:.2f} s on 1 thread"}
 
 
 def kernel_key(name):
@@ -170,23 +235,36 @@ def traffic_for(workload, kernel):
     return ent.get("bytes_per_launch") if ent else None
 
 
-def best_device_copy(x, y, nbytes, stream):
-    """Fastest of the copy kernel's variants and hipMemcpy (device to device)."""
+def best_device_copy(x, y, nbytes, stream, flush=None, reps=10):
+    """Fastest of the copy kernel's variants and hipMemcpy (device to device):
+    back to back (flush None), or each call after a cache flush."""
     from paper_2306_07795_amd import binding as B
+
+    def t(fn):
+        if flush is None:
+            return timed(fn, reps, 2, stream)
+        return mean(flushed_times(fn, reps, 2, stream, flush))
     best = (1e30, None)
     for vpt in (1, 2, 4, 8):
         for hints in (0, 1, 2, 3):
-            ms = timed(lambda: B.bmmc_copy_ex(x, y, nbytes, vpt, hints, stream), 10, 2, stream)
+            ms = t(lambda: B.bmmc_copy_ex(x, y, nbytes, vpt, hints, stream))
             best = min(best, (ms, f"k_copy vpt={vpt} hints={hints}"))
-    ms = timed(lambda: y.copy_(x), 10, 2, stream)
+    ms = t(lambda: y.copy_(x))
     best = min(best, (ms, "hipMemcpy device to device"))
     return best
 
 
-def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True, retune=False):
+def dominant(kstats):
+    """(name, stats) of the kernel with the most time, flush copies excluded."""
+    ks = {k: v for k, v in kstats.items() if k != FLUSH_KERNEL}
+    return max(ks.items(), key=lambda kv: kv[1]["total_ms"])
+
+
+def paper_two_pass(x, y, n, rows, c, w, stream, flush, copy_ms, warm_copy_ms, tune=True, retune=False):
     """The paper's scheme on the same input: the factorization into tiled
     BMMCs, two LDS-staged passes through scratch (Section 5.2), tuned the
-    same way; with its dominant kernel's per-launch rate."""
+    same way; each call after a cache flush (and back to back), with its
+    dominant kernel's rate per launch (kernel-bound events)."""
     from paper_2306_07795_amd import binding as B
     nbytes = (1 << n) * w
     opts = {"method": B.METHOD_TILED}
@@ -197,49 +275,40 @@ def paper_two_pass(x, y, n, rows, c, w, stream, dev_copy, tune=True, retune=Fals
             found = B.bmmc_tune_lookup(n, w, rows, B.METHOD_TILED)
         opts = found or opts
     passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
-    ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 3, stream)
     B.bmmc_profile_begin()
-    for _ in range(20):
-        B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
-    torch_sync()
-    ks = B.bmmc_profile_end()
-    kname, k = max(ks.items(), key=lambda kv: kv[1]["total_ms"])
-    # both passes are the same kernel: the time per launch of the plain loop
-    per_launch = ms * 20 / k["launches"] if len(ks) == 1 else k["total_ms"] / k["launches"]
+    ms = mean(flushed_times(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 3, stream, flush))
+    kname, k = dominant(B.bmmc_profile_end())
+    warm_ms = timed(lambda: B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream), 20, 3, stream)
     v = gbps(nbytes, ms)
-    return {"GBps": round(v, 1), "passes": passes, "pct_of_device_copy": round(100.0 * v / dev_copy, 2),
-            "traffic_pct_of_device_copy": round(100.0 * v * passes / dev_copy, 2),
-            "kernel": kname, "kernel_GBps": round(k["bytes"] / k["launches"] / (per_launch * 1e-3) / 1e9, 1),
+    per_launch = k["total_ms"] / k["launches"]
+    return {"GBps": round(v, 1), "passes": passes, "pct_of_device_copy": round(100.0 * copy_ms / ms, 2),
+            "traffic_pct_of_device_copy": round(100.0 * copy_ms * passes / ms, 2),
+            "kernel": kname, "kernel_mean_launch_ms": round(per_launch, 5),
+            "kernel_GBps": round(k["bytes"] / k["launches"] / (per_launch * 1e-3) / 1e9, 1),
+            "warm": {"GBps": round(gbps(nbytes, warm_ms), 1),
+                     "pct_of_device_copy": round(100.0 * warm_copy_ms / warm_ms, 2)},
             "options": opts}
 
 
-def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, reps=20):
-    """The permutation and the copy bound outside the steady state of the
-    timed loop (which repeats one call on the same buffers, so that part of a
-    2^26-element array stays in the 256 MB last-level cache between calls):
-    "chained" alternates x -> m and m -> y, so that every call reads what the
-    call before it has just written; "flushed" copies 1 GiB elsewhere before
-    every call (events around the call only), which leaves the caches full
-    of another array's dirty lines.  The permutation runs with the timed
-    options, and with them but non-temporal loads and cached stores (hints
-    1) or non-temporal loads and stores (hints 3); the copy is the fastest
-    of its variants in the same state."""
+def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, flush, reps=20):
+    """The permutation and the copy bound in two other states than the
+    headline's: "chained" alternates x -> m and m -> y, so that every call
+    reads what the call before it has just written, as in a pipeline; and,
+    after a cache flush like the headline, the timed options against
+    non-temporal loads with cached stores (hints 1) and non-temporal loads
+    and stores (hints 3).  Events around each call only; the copy is the
+    fastest of its variants in the same state."""
     import torch
     from paper_2306_07795_amd import binding as B
     nbytes = (1 << n) * w
     m = torch.empty_like(x)
-    j1 = torch.empty(1 << 30, dtype=torch.uint8, device=x.device)
-    j2 = torch.empty_like(j1)
-
-    def flush():
-        B.bmmc_copy_ex(j1, j2, 1 << 30, 1, 0, stream)
 
     def per_call(fns, before=None):
         evs = []
         for r in range(reps + 2):
             for fn in fns:
                 if before:
-                    before()
+                    before(stream)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
                 fn()
@@ -269,21 +338,22 @@ def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, reps=20):
                       "pct_of_copy": {k: round(100.0 * cp_us / v, 1) for k, v in p_us.items()},
                       "paper_two_pass_us": round(t_us, 1),
                       "one_pass_speedup_vs_two": round(t_us / min(p_us.values()), 2)}
-    del m, j1, j2
+    del m
     return out
 
 
-def other_matrices(x, y, n, w, copy_ms, stream, seeds=8, reps=10):
+def other_matrices(x, y, n, w, copy_ms, stream, flush, seeds=8, reps=10):
     """The library's default call on random matrices of seeds 0..seeds-1 (the
-    timed workload is seed 0), then the same after tuning each matrix:
-    beyond the last-level cache how the accesses meet the memory system
-    varies from one matrix to another."""
+    timed workload is seed 0), each call after a cache flush like the
+    headline, then the same after tuning each matrix: beyond the last-level
+    cache how the accesses meet the memory system varies from one matrix to
+    another."""
     from paper_2306_07795_amd import binding as B
     from synth import gen
     pct, per = [], []
     for seed in range(seeds):
         rows, c = gen.random_bmmc(n, seed)
-        ms = timed(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream)
+        ms = mean(flushed_times(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream, flush))
         pct.append(100.0 * copy_ms / ms)
     # the same calls after bmmc_autotune_matrix has tuned each matrix
     # (before the timed calls; the settings are dropped afterwards)
@@ -291,7 +361,7 @@ def other_matrices(x, y, n, w, copy_ms, stream, seeds=8, reps=10):
         for seed in range(seeds):
             rows, c = gen.random_bmmc(n, seed)
             B.bmmc_autotune_matrix(x, y, n, rows, c, w, stream, 3)
-            ms = timed(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream)
+            ms = mean(flushed_times(lambda: B.bmmc_permute(x, y, n, rows, c, w, stream), reps, 2, stream, flush))
             per.append(100.0 * copy_ms / ms)
     finally:
         B.bmmc_tune_clear_matrices()
@@ -299,7 +369,7 @@ def other_matrices(x, y, n, w, copy_ms, stream, seeds=8, reps=10):
     def summary(v):
         return {"pct_of_device_copy": [round(p, 1) for p in v], "mean": round(sum(v) / len(v), 1),
                 "min": round(min(v), 1), "max": round(max(v), 1)}
-    return {"seeds": f"0-{seeds - 1}", **summary(pct), "tuned_per_matrix": summary(per)}
+    return {"seeds": f"0-{seeds - 1}", "cache_state": "flushed", **summary(pct), "tuned_per_matrix": summary(per)}
 
 
 def torch_sync():
@@ -308,10 +378,14 @@ def torch_sync():
 
 
 def bench_batched(count=1024, reps=50, seed=0, retune=False):
-    """1024 arrays, n uniform in [10, 22], int32, each its own A and c: one
-    graph-launched persistent kernel against 1024 separate bmmc_permute calls
-    on one stream (arguments marshalled once for both).  Batch latency = one
-    launch's events; p50/p99 over reps."""
+    """1024 arrays, n uniform in [10, 22], int32, each its own A and c: the
+    resident batch (one graph replay of the persistent kernel) against the
+    same 1024 arrays as separate bmmc_permute calls, both issued by the host
+    (a ctypes loop) and captured once into a graph of 1024 launches and
+    replayed (device time of separate launches, no host issue cost).  Batch
+    latency = events around one launch or replay; p50/p99 over reps."""
+    import ctypes
+
     import numpy as np
     import torch
     from paper_2306_07795_amd import binding as B
@@ -320,7 +394,7 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     items, total = [], 0
     for k, n in enumerate(sizes):
         rows, c = gen.random_bmmc(n, 1_000_003 * (seed + 1) + k)
-        x = torch.randint(0, 1 << 30, (1 << n,), dtype=torch.int32, device="cuda")
+        x = torch.from_numpy(gen.data(n, 4, k).view(np.uint8)).to("cuda")
         y = torch.empty_like(x)
         items.append((x, y, n, 4, rows, c))
         total += (1 << n) * 4
@@ -352,17 +426,26 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     oneshot = lat(lambda: B.bmmc_permute_batched(descs, stream, tuned), max(5, reps // 5))
 
     # 1024 separate library calls, their arguments marshalled once
-    import ctypes
-    lib, sp = B.lib(), ctypes.c_void_p(stream.cuda_stream)
+    lib = B.lib()
     calls = [(ctypes.c_void_p(it[0].data_ptr()), ctypes.c_void_p(it[1].data_ptr()), it[2],
               (ctypes.c_uint64 * it[2])(*[int(v) for v in it[4]]), ctypes.c_uint64(it[5])) for it in items]
 
-    def separate():
+    def separate(s):
+        sp = ctypes.c_void_p(s.cuda_stream)
         for i, o, n, r, c in calls:
             if lib.bmmc_permute(i, o, n, r, c, 4, sp) != 0:
                 raise SystemExit("bmmc_permute failed: " + lib.bmmc_last_error().decode())
 
-    sep = lat(separate, max(5, reps // 5))
+    sep = lat(lambda: separate(stream), max(5, reps // 5))
+    # the same 1024 calls captured into one graph (plans made by the calls
+    # above; one-pass plans need no scratch) and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        separate(torch.cuda.current_stream())
+    g.replay()
+    torch.cuda.synchronize()
+    sep_graph = lat(g.replay, reps)
+    del g
     pb.close()
     # the copy bound at the batch's size: one copy of as many bytes (the
     # batch's 2.6 GB each way do not fit the last-level cache, unlike the
@@ -372,61 +455,103 @@ def bench_batched(count=1024, reps=50, seed=0, retune=False):
     copy_ms, copy_how = best_device_copy(cx, cy, total, stream)
     del cx, cy
     med = float(np.median(resident))
+
+    def p(v, q):
+        return round(float(np.percentile(v, q)), 4)
     return {
         "arrays": count, "bytes_per_side": total,
         "GBps": round(gbps(total, med), 1),
         "device_copy_same_bytes_GBps": round(gbps(total, copy_ms), 1),
         "pct_of_device_copy_same_bytes": round(100.0 * copy_ms / med, 1),
-        "p50_ms": round(med, 4), "p99_ms": round(float(np.percentile(resident, 99)), 4),
-        "oneshot_p50_ms": round(float(np.median(oneshot)), 4),
+        "p50_ms": round(med, 4), "p99_ms": p(resident, 99),
+        "oneshot_p50_ms": p(oneshot, 50),
         "oneshot_GBps": round(gbps(total, float(np.median(oneshot))), 1),
         "separate_launches_GBps": round(gbps(total, float(np.median(sep))), 1),
-        "separate_p50_ms": round(float(np.median(sep)), 4),
-        "separate_p99_ms": round(float(np.percentile(sep, 99)), 4),
+        "separate_p50_ms": p(sep, 50), "separate_p99_ms": p(sep, 99),
+        "separate_graph_GBps": round(gbps(total, float(np.median(sep_graph))), 1),
+        "separate_graph_p50_ms": p(sep_graph, 50), "separate_graph_p99_ms": p(sep_graph, 99),
         "speedup_vs_separate": round(float(np.median(sep)) / med, 2),
+        "speedup_vs_separate_graph": round(float(np.median(sep_graph)) / med, 2),
         "tuned": tuned,
     }
 
 
-def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0, solo_log2=0,
-                 streams=4):
-    """Open-loop Poisson arrivals at `rate` requests/s for `seconds`: n uniform
-    in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs resident in
-    a pool per (n, width); outputs and scratch from the server's HBM budget.
-    A quarter second of warm-up requests runs first, outside the statistics."""
+def _bmmc_chunk(specs):
+    from synth import gen
+    return [gen.random_bmmc(n, sd) for n, sd in specs]
+
+
+def random_matrices(specs):
+    """gen.random_bmmc(n, seed) for every (n, seed), on a few worker
+    processes when there are many (started fresh: they never touch the
+    GPU)."""
+    if len(specs) < 50000:
+        return _bmmc_chunk(specs)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    step = 20000
+    chunks = [specs[i:i + step] for i in range(0, len(specs), step)]
+    with cf.ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("spawn")) as ex:
+        out = []
+        for part in ex.map(_bmmc_chunk, chunks):
+            out.extend(part)
+    return out
+
+
+def served_stats(st, reqs, seconds):
+    offered = sum((1 << r["n"]) * r["w"] for r in reqs)
+    return {"completed": st["completed"], "rejected": st["rejected"],
+            "GBps": round(st["bytes_moved"] / max(st["busy_s"], 1e-9) / 1e9, 1),
+            "offered_GBps": round(2.0 * offered / reqs[-1]["arrival"] / 1e9, 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+            "mean_batch": round(st["mean_batch"], 2), "launches": st["batches"],
+            "mean_plan_ms": round(st["mean_plan_ms"], 3), "mean_wait_ms": round(st["mean_wait_ms"], 3),
+            "mean_run_ms": round(st["mean_run_ms"], 3), "busy_s": round(st["busy_s"], 3)}
+
+
+def bench_served(rate=20000.0, seconds=10.0, warm_s=1.0, budget=64 << 30, seed=0, use_graph=0, direct_max=0,
+                 solo_log2=0, streams=4, baselines=(1, 4)):
+    """Open-loop Poisson arrivals at `rate` requests/s for `seconds` after
+    `warm_s` of warm-up requests (other matrices, outside the statistics): n
+    uniform in [12, 26], 4- or 8-byte elements, a random BMMC each; inputs
+    resident in a pool per (n, width).  The server (continuous batching,
+    outputs and scratch from its HBM budget) and then, on the same requests,
+    the unbatched baseline: each request its own bmmc_permute at its arrival,
+    on 1 and on 4 streams (bmmc_serve_direct; outputs in a buffer per stream
+    and size)."""
     import torch
     from paper_2306_07795_amd import binding as B
     from synth import gen
     count = int(rate * seconds)
     reqs = gen.poisson_requests(count, rate, seed, 12, 26, (4, 8))
+    warm = gen.poisson_requests(max(1, int(rate * warm_s)), rate, seed + 7919, 12, 26, (4, 8))
+    mats = random_matrices([(r["n"], r["seed"]) for r in reqs])
+    warm_mats = random_matrices([(r["n"], r["seed"] + 7919) for r in warm])
     pool = {}
     for n in range(12, 27):
         for w in (4, 8):
             pool[(n, w)] = torch.randint(0, 255, ((1 << n) * w,), dtype=torch.uint8, device="cuda")
-    mats = {}
-    for r in reqs:
-        mats[r["id"]] = gen.random_bmmc(r["n"], r["seed"])
     torch.cuda.synchronize()
+
+    def marshal(rs, ms, outs=None, lanes=1):
+        return B.DescBatch([(pool[(r["n"], r["w"])], None if outs is None else outs[k % lanes][(r["n"], r["w"])],
+                             r["n"], r["w"], m[0], m[1]) for k, (r, m) in enumerate(zip(rs, ms))])
+
+    out = {"rate_req_s": rate, "requests": count, "seconds": seconds, "warmup_s": warm_s}
     srv = B.bmmc_server_create(budget, streams=streams, own_outputs=2, use_graph=use_graph, direct_max=direct_max,
                                solo_log2=solo_log2)
     try:
-        # warm-up: a quarter second of the same stream (other matrices), then
-        # the statistics start afresh
-        warm = gen.poisson_requests(max(1, int(rate * 0.25)), rate, seed + 7919, 12, 26, (4, 8))
-        start = B.bmmc_server_now_ns() + int(0.1e9)
-        for r in warm:
-            rows, c = gen.random_bmmc(r["n"], r["seed"] + 7919)
-            B.bmmc_server_submit(srv, pool[(r["n"], r["w"])], 0, r["n"], rows, c, r["w"],
-                                 start + int(r["arrival"] * 1e9))
+        # warm-up, then the statistics start afresh; every request is
+        # marshalled before the clock starts and submitted ahead of its
+        # arrival time (the server plans and launches it only once that time
+        # has come), so that the submitting loop never lags behind
+        wd = marshal(warm, warm_mats)
+        start = B.bmmc_server_now_ns() + int(0.2e9)
+        B.bmmc_server_submit_many(srv, wd, [start + int(r["arrival"] * 1e9) for r in warm])
         B.bmmc_server_drain(srv)
         B.bmmc_server_reset_stats(srv)
-        # every request is marshalled before the clock starts and submitted
-        # ahead of its arrival time (the server plans and launches it only
-        # once that time has come), so that the submitting loop never lags
-        # behind the arrivals
-        descs = B.DescBatch([(pool[(r["n"], r["w"])], None, r["n"], r["w"], mats[r["id"]][0], mats[r["id"]][1])
-                             for r in reqs])
-        lead = 0.5
+        descs = marshal(reqs, mats)
+        lead = 1.0
         start = B.bmmc_server_now_ns() + int(lead * 1e9)
         B.bmmc_server_submit_many(srv, descs, [start + int(r["arrival"] * 1e9) for r in reqs])
         submit_s = (B.bmmc_server_now_ns() - start) * 1e-9 + lead
@@ -436,43 +561,57 @@ def bench_served(rate=20000.0, seconds=2.0, budget=64 << 30, seed=0, use_graph=0
         st = B.bmmc_server_stats(srv)
     finally:
         B.bmmc_server_destroy(srv)
-    offered = sum((1 << r["n"]) * r["w"] for r in reqs)
-    return {
-        "rate_req_s": rate, "requests": count, "completed": st["completed"], "rejected": st["rejected"],
-        "GBps": round(st["bytes_moved"] / max(st["busy_s"], 1e-9) / 1e9, 1),
-        "offered_GBps": round(2.0 * offered / (reqs[-1]["arrival"]) / 1e9, 1),
-        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-        "mean_batch": round(st["mean_batch"], 1), "launches": st["batches"],
-        "mean_plan_ms": round(st["mean_plan_ms"], 3), "mean_wait_ms": round(st["mean_wait_ms"], 3),
-        "mean_run_ms": round(st["mean_run_ms"], 3),
-        "peak_budget_GB": round(st["peak_bytes"] / 1e9, 2),
-        "submit_s": round(submit_s, 3),
-    }
+    out.update(served_stats(st, reqs, seconds))
+    out["peak_budget_GB"] = round(st["peak_bytes"] / 1e9, 2)
+    out["streams"] = streams
+    del descs
+    torch.cuda.empty_cache()
+    for lanes in baselines:
+        outs = [{(n, w): torch.empty((1 << n) * w, dtype=torch.uint8, device="cuda")
+                 for n in range(12, 27) for w in (4, 8)} for _ in range(lanes)]
+        wd = marshal(warm, warm_mats, outs, lanes)
+        start = B.bmmc_server_now_ns() + int(0.2e9)
+        B.bmmc_serve_direct(wd, [start + int(r["arrival"] * 1e9) for r in warm], lanes)
+        d = marshal(reqs, mats, outs, lanes)
+        start = B.bmmc_server_now_ns() + int(0.2e9)
+        st = B.bmmc_serve_direct(d, [start + int(r["arrival"] * 1e9) for r in reqs], lanes)
+        out[f"per_request_{lanes}_stream{'s' if lanes > 1 else ''}"] = served_stats(st, reqs, seconds)
+        del outs, d, wd
+        torch.cuda.empty_cache()
+    return out
 
 
-def transpose_sweep(n=25, w=4, steps=20):
+def transpose_sweep(n=25, w=4, steps=10):
     """The paper's AMD experiment (Section 6, transpose time against the
     number of columns at a fixed 2^25 elements), on this GPU: for every split
-    k, the 2^(n-k) x 2^k matrix transpose (bit-block swap, one tiled pass),
-    the naive kernel and the device copy."""
+    k, the 2^(n-k) x 2^k matrix transpose (bit-block swap, one tiled pass) by
+    the library's default call, the naive kernel and the device copy, each
+    call after a cache flush (as the headline); the tiled pass's own kernel
+    duration from events bound to its launches."""
     import torch
     from paper_2306_07795_amd import binding as B
     from synth import gen
     nbytes = (1 << n) * w
-    x = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    x = torch.from_numpy(gen.data(n, w, 0).view("uint8")).to("cuda")
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-    copy_ms, _ = best_device_copy(x, y, nbytes, stream)
+    flush = Flusher(x.device)
+    copy_ms, copy_how = best_device_copy(x, y, nbytes, stream, flush)
     table = []
     for k in range(n + 1):
         rows = gen.block_swap_rows(n, k)
-        t_ms = timed(lambda: B.bmmc_permute(x, y, n, rows, 0, w, stream), steps, 2, stream)
-        nv_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, 0, w, stream), steps, 2, stream)
+        B.bmmc_profile_begin()
+        t_ms = mean(flushed_times(lambda: B.bmmc_permute(x, y, n, rows, 0, w, stream), steps, 2, stream, flush))
+        kname, ks = dominant(B.bmmc_profile_end())
+        nv_ms = mean(flushed_times(lambda: B.bmmc_permute_naive(x, y, n, rows, 0, w, stream), 3, 1, stream, flush))
         table.append({"k": k, "columns": 1 << k, "rows": 1 << (n - k),
                       "tiled_us": round(t_ms * 1e3, 2), "tiled_GBps": round(gbps(nbytes, t_ms), 1),
                       "tiled_pct_of_copy": round(100.0 * copy_ms / t_ms, 1),
+                      "kernel": kname, "kernel_us": round(1e3 * ks["total_ms"] / ks["launches"], 2),
                       "naive_us": round(nv_ms * 1e3, 2), "naive_GBps": round(gbps(nbytes, nv_ms), 1)})
-    return {"n": n, "elem_bytes": w, "copy_us": round(copy_ms * 1e3, 2), "table": table}
+        progress(f"transpose k={k}: {table[-1]['tiled_pct_of_copy']} % of copy")
+    return {"n": n, "elem_bytes": w, "cache_state": "flushed before every call", "copy_us": round(copy_ms * 1e3, 2),
+            "copy": copy_how, "table": table}
 
 
 def sortnet_table(sizes=(12, 16, 20, 24, 26), seed=0):
@@ -516,6 +655,22 @@ def sortnet_table(sizes=(12, 16, 20, 24, 26), seed=0):
 
 
 CACHE_RESIDENT_BYTES = 64 << 20
+
+
+def sanity(B, x, y, n, rows, c, w, step, stream):
+    """What is timed is a permutation of the input: the inverse, run by the
+    library's default path, restores it (parity with the oracle is the
+    tests' job)."""
+    import torch
+    step()
+    inv_rows, inv_c = B.bmmc_invert(rows, c, n)
+    z = torch.empty_like(x)
+    B.bmmc_permute(y, z, n, inv_rows, inv_c, w, stream)
+    torch.cuda.synchronize()
+    if not torch.equal(z, x):
+        print("bench: the inverse permutation does not restore the input", file=sys.stderr)
+        sys.exit(1)
+    del z
 
 
 def graph_time(fn, steps, warmup):
@@ -600,7 +755,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-rate", type=float, default=20000.0)
-    ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--extras-out", default=None, help="write extra measurements (JSON) here")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc runs of this "
@@ -610,8 +765,7 @@ def main():
     ap.add_argument("--sortnet", action="store_true",
                     help="print the sorting-network table (compiled passes vs direct) and exit")
     ap.add_argument("--served-sweep", action="store_true",
-                    help="print the served form at 5k, 10k, 15k and 20k requests/s (and at 20k "
-                         "with batched launches only, and without single-array plans) and exit")
+                    help="print the served form and its per-request baselines at 10k-80k requests/s and exit")
     args = ap.parse_args()
     if args.transpose_sweep:
         print(json.dumps(transpose_sweep()), flush=True)
@@ -620,14 +774,12 @@ def main():
         print(json.dumps(sortnet_table()), flush=True)
         return
     if args.served_sweep:
-        rows = [dict(bench_served(rate, args.served_seconds), mode="default")
-                for rate in (5000.0, 10000.0, 15000.0, 20000.0)]
-        rows += [dict(bench_served(20000.0, args.served_seconds, direct_max=-1, use_graph=g),
-                      mode="batched launches only" + (", graph replay" if g else ""))
-                 for g in (0, 1)]
-        rows += [dict(bench_served(20000.0, args.served_seconds, solo_log2=-1),
-                      mode="no request planned as a single-array call")]
-        print(json.dumps({"workload": "served load sweep", "table": rows}), flush=True)
+        rows = []
+        for rate in (10000.0, 20000.0, 40000.0, 60000.0, 80000.0):
+            rows.append(bench_served(rate, args.served_seconds))
+            progress(f"served at {rate:.0f} requests/s: {json.dumps(rows[-1])}")
+        print(json.dumps({"workload": "served load sweep: server (4 streams) against per-request launches on "
+                                      "1 and 4 streams, same Poisson requests", "table": rows}), flush=True)
         return
     if args.traffic_from:
         n, w = WORKLOADS[args.workload][:2]
@@ -681,72 +833,80 @@ def main():
     def step():
         B.bmmc_permute_ex(x, y, n, rows, c, w, opts, stream)
 
-    # sanity of what is timed (parity with the oracle is the tests' job): the
-    # inverse permutation, run by the library's default path, restores the input
-    step()
-    inv_rows, inv_c = B.bmmc_invert(rows, c, n)
-    z = torch.empty_like(x)
-    B.bmmc_permute(y, z, n, inv_rows, inv_c, w, stream)
-    torch.cuda.synchronize()
-    if not torch.equal(z, x):
-        print("bench: the inverse permutation does not restore the input", file=sys.stderr)
-        sys.exit(1)
-    del z
-
     if nbytes < CACHE_RESIDENT_BYTES:
+        sanity(B, x, y, n, rows, c, w, step, stream)
         graph_timed_line(args, n, w, rows, c, opts, tuned, desc, x, y, nbytes, passes, stream)
         if args.save_tune:
             B.bmmc_tune_save(args.save_tune)
         return
 
-    # timed region: exactly `steps` permutations, HIP events on the stream at
-    # its two ends only (events around every launch would add their own
-    # commands between the kernels: about 7 us per step here)
+    # timed region: exactly `steps` permutations, each right after a cache
+    # flush (outside the timed interval); HIP events on the stream around
+    # each step.  The library's profiling binds a second pair of events to
+    # every kernel it launches, which gives each launch's own duration.
+    flush = Flusher(dev)
     for _ in range(args.warmup):
+        flush(stream)
         step()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    value = gbps(nbytes, ms)
-    # which kernels a step launches, and each launch's own duration: the same
-    # steps again with events around every launch
     B.bmmc_profile_begin()
+    evs = []
     for _ in range(args.steps):
+        flush(stream)
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
         step()
+        eb.record(stream)
+        evs.append((ea, eb))
     torch.cuda.synchronize()
     kstats = B.bmmc_profile_end()
+    step_ms = [ea.elapsed_time(eb) for ea, eb in evs]
+    ms = mean(step_ms)
+    value = gbps(nbytes, ms)
+    progress(f"timed steps: {ms:.5f} ms per step, {value:.1f} GB/s (flushed)")
 
-    # bounds in the same session
-    copy_ms, copy_how = best_device_copy(x, y, nbytes, stream)
+    # the copy bound in the same state and session
+    copy_ms, copy_how = best_device_copy(x, y, nbytes, stream, flush)
+    dev_copy = gbps(nbytes, copy_ms)
+    extras = {"device_copy": copy_how, "step_ms_min": round(min(step_ms), 5),
+              "step_ms_max": round(max(step_ms), 5)}
+    if not args.no_extras:
+        # the steady state of one call repeated on the same buffers (part of
+        # an array that fits the 256 MB last-level cache stays there between
+        # calls), against a copy repeated the same way
+        warm_ms = timed(step, args.steps, args.warmup, stream)
+        B.bmmc_profile_begin()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wname, wk = dominant(B.bmmc_profile_end())
+        warm_copy_ms, warm_copy_how = best_device_copy(x, y, nbytes, stream)
+        extras["warm"] = {"GBps": round(gbps(nbytes, warm_ms), 1), "ms_per_step": round(warm_ms, 5),
+                          "device_copy_GBps": round(gbps(nbytes, warm_copy_ms), 1), "device_copy": warm_copy_how,
+                          "pct_of_device_copy": round(100.0 * warm_copy_ms / warm_ms, 2),
+                          "kernel": wname, "kernel_mean_launch_ms": round(wk["total_ms"] / wk["launches"], 5)}
     # the traffic calibration kernel, k_copy<4,0>, launched at least once
     B.bmmc_copy_ex(x, y, nbytes, 4, 0, stream)
-    dev_copy = gbps(nbytes, copy_ms)
-    extras = {"device_copy": copy_how}
     if method == B.METHOD_AUTO and not args.no_extras:
-        naive_ms = timed(lambda: B.bmmc_permute_naive(x, y, n, rows, c, w, stream), 10, 2, stream)
+        naive_ms = mean(flushed_times(lambda: B.bmmc_permute_naive(x, y, n, rows, c, w, stream), 5, 1, stream,
+                                      flush))
         extras["naive_GBps"] = round(gbps(nbytes, naive_ms), 1)
-        extras["paper_two_pass"] = paper_two_pass(x, y, n, rows, c, w, stream, dev_copy,
+        extras["paper_two_pass"] = paper_two_pass(x, y, n, rows, c, w, stream, flush, copy_ms, warm_copy_ms,
                                                   tune=not (args.no_tune or args.options_from),
                                                   retune=args.retune)
         extras["cache_state"] = cache_states(x, y, n, rows, c, w, opts, extras["paper_two_pass"]["options"],
-                                             stream)
+                                             stream, flush)
         if kind == "random":
-            extras["random_matrices"] = other_matrices(x, y, n, w, copy_ms, stream)
+            extras["random_matrices"] = other_matrices(x, y, n, w, copy_ms, stream, flush)
+    # parity with the oracle is the tests' job; this checks that what was
+    # timed is a permutation of the input: the inverse, by the library's
+    # default path, restores it
+    sanity(B, x, y, n, rows, c, w, step, stream)
 
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean
-    # launch time.  When every launch of a step is that kernel, the mean
-    # launch time is the timed region's time per launch (dispatch gaps
-    # included); otherwise the per-launch events give it.
-    dname, d = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
-    events_ms = d["total_ms"] / d["launches"]
-    launches_per_step = d["launches"] / args.steps
-    per_launch_ms = ms / launches_per_step if len(kstats) == 1 else events_ms
+    # roofline of the dominant kernel: algorithmic bytes per launch / its
+    # mean launch duration (kernel-bound events of the timed steps)
+    dname, d = dominant(kstats)
+    per_launch_ms = d["total_ms"] / d["launches"]
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
     tbytes = traffic_for(args.workload, dname)
@@ -756,8 +916,8 @@ def main():
                 "traffic": None if tbytes is None else round(tbytes / (per_launch_ms * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": tbytes,
                 "kernel": dname, "launches": d["launches"], "mean_launch_ms": round(per_launch_ms, 5),
-                "mean_launch_ms_events": round(events_ms, 5),
-                "launch_time_from": "timed region / launches" if len(kstats) == 1 else "per-launch events",
+                "launch_time_from": "events bound to each launch of the timed steps (hipExtLaunchKernel)",
+                "cache_state": "flushed before every step",
                 "bytes_per_launch": launch_bytes}
 
     line = {
@@ -766,7 +926,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "elem_bytes": w, "method": args.method,
-                   "passes": passes, "seed": 0, "options": tuned, "tuning": tuning},
+                   "passes": passes, "seed": 0, "options": tuned, "tuning": tuning,
+                   "cache_state": f"flushed: a {FLUSH_BYTES >> 20} MiB copy between two other buffers before "
+                                  "every step, outside the timed interval (the copy bound likewise)"},
         "pct_of_device_copy": round(100.0 * value / dev_copy, 2),
         "pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBPS, 2),
         "device_copy_GBps": round(dev_copy, 1),
@@ -775,14 +937,17 @@ def main():
         "roofline": roofline,
         "extras": extras,
     }
-    del x, y
+    del x, y, flush
     torch.cuda.empty_cache()
+    progress("single-array extras done")
     if not args.no_batched and not args.no_extras:
         line["batched"] = bench_batched(retune=args.retune)
         torch.cuda.empty_cache()
+        progress("batched done")
     if not args.no_served and not args.no_extras:
         line["served"] = bench_served(args.served_rate, args.served_seconds)
         torch.cuda.empty_cache()
+        progress("served done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a, n, rows, c)
     if args.extras_out:

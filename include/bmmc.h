@@ -301,13 +301,14 @@ int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint6
 
 /* ------------------------------------------------------- device calls */
 
-/* The permutation out[A.x XOR c] = in[x] (Section 2), by BMMC_METHOD_AUTO
-   with the options bmmc_autotune stored for (n, elem_bytes) and the class of
-   A, else with the size-dependent defaults.  These are tuned for a call
-   repeated on the same buffers; where each call reads what the one before
-   it wrote, non-temporal loads with cached stores (hints 1, through
-   bmmc_permute_ex) are faster for arrays that fit the last-level cache.
-   Plans are cached
+/* The permutation out[A.x XOR c] = in[x]: the affine map x -> A.x XOR c over
+   F_2 of Section 3, applied in the scatter direction of the Section 4.1
+   kernel (the element read at x is written at A.x XOR c).  Runs by
+   BMMC_METHOD_AUTO with the options bmmc_autotune stored for (n, elem_bytes)
+   and the class of A, else with the size-dependent defaults.  From 64 MiB on
+   these are tuned for a call that finds the caches full of other data (the
+   tuner flushes them before every timed call); below, for calls repeated on
+   arrays that stay in the caches.  Plans are cached
    by (A, c, n, elem_bytes, options); two-pass plans (BMMC_METHOD_TILED) use a
    scratch array of 2^n * elem_bytes owned by the library (kept per device
    and stream, grown on demand).
@@ -375,8 +376,11 @@ int bmmc_batch_destroy(void* handle);
    fastest of each class is cached for (n, elem_bytes, method, class) and used
    by later calls that pass no options, by the class of their matrix; class
    0's is also returned.  Below 64 MiB the `reps` calls of a candidate are
-   captured into a graph (on a stream of its own) and the replay is timed.
-   Allocates two temporary buffers of 2^n * elem_bytes.
+   captured into a graph (on a stream of its own) and the replay is timed;
+   from 64 MiB on each call is timed on its own right after a 512 MiB copy
+   between two other buffers, which leaves the caches full of other data.
+   Allocates two temporary buffers of 2^n * elem_bytes (and two of 512 MiB
+   from 64 MiB on).
    Errors: _RANGE, _ARG, _NOMEM, _HIP. */
 int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
                   bmmc_options_t* best_out, double* best_ms);
@@ -388,7 +392,8 @@ int bmmc_autotune(int n, int elem_bytes, int method, void* stream, int reps,
    defaults).  Host only.  Errors: _ARG, _RANGE. */
 int bmmc_tune_lookup(int n, int elem_bytes, int method, const uint64_t* A_rows, bmmc_options_t* opts_out);
 
-/* Tune for one matrix (Section 2 permutation, BMMC_METHOD_AUTO): times, on
+/* Tune for one matrix (the permutation of bmmc_permute, Section 3 map in the
+   Section 4.1 scatter direction; BMMC_METHOD_AUTO): times, on
    these buffers, the options a call would use now under every tile order,
    then a few other tile shapes (4- and 8-byte elements), and keeps the
    fastest for later bmmc_permute calls (and served requests planned as
@@ -486,7 +491,9 @@ int bmmc_server_submit(void* handle, const bmmc_desc_t* desc, int64_t arrival_ns
 
 /* State of a ticket: BMMC_OK with the completion time and output pointer,
    BMMC_ERR_BUSY while pending (wait = 0), or the error the request failed
-   with.  wait != 0 blocks until completion. */
+   with.  wait != 0 blocks until completion.  With own_outputs == 2 a
+   request is forgotten when it finishes: its ticket then reads
+   BMMC_ERR_NOTFOUND, and wait != 0 is refused with BMMC_ERR_ARG. */
 int bmmc_server_poll(void* handle, int64_t ticket, int wait, int64_t* done_ns, void** out_ptr);
 
 /* Forget a finished ticket and free its output (own_outputs == 1). */
@@ -508,11 +515,32 @@ int bmmc_server_destroy(void* handle);
 /* The server's clock (steady clock, nanoseconds). */
 int64_t bmmc_server_now_ns(void);
 
+/* The unbatched baseline of the server, on the same request stream: request
+   k runs as its own bmmc_permute call, issued at arrival_ns[k] (server
+   clock) on stream k mod `streams` by that stream's issuing thread (one per
+   stream, each planning its own requests), with no admission and no
+   batching; a second thread per stream stamps each request's completion
+   when an event recorded after it has passed.  Requests of one stream run in
+   order, so they may share an output buffer; every descriptor obeys the
+   rules of bmmc_permute.  Blocks until every request has completed and
+   fills *stats_out as bmmc_server_stats does (one launch per request; plan
+   time = arrival to the call's return, run time = return to completion;
+   no budget figures).  streams: 1..16 (0: 4).  Creates and destroys its
+   own streams.  Errors: _ARG, _RANGE, _HIP, or the first request's error
+   (the others still run). */
+int bmmc_serve_direct(const bmmc_desc_t* descs, const int64_t* arrival_ns, int count, int streams,
+                      bmmc_server_stats_t* stats_out);
+
 /* ------------------------------------------------------------ profiling */
 
-/* Start recording a hipEvent pair around every kernel launch the library
-   makes on this device; bmmc_profile_end waits for them, fills up to `max`
-   entries (one per kernel name) and returns how many it filled. */
+/* Start timing every launch the library makes on this device: a hipEvent
+   pair bound to each single kernel's own dispatch (hipExtLaunchKernel; the
+   interval is the kernel's execution and nothing is enqueued between
+   kernels), or recorded around a batched launch's graph or kernels.
+   Launches onto a stream under capture are not timed.  bmmc_profile_end
+   waits for the events, fills up to `max` entries (one per kernel name, e.g.
+   "k_tiled<4,512,8,3>", "k_copy<vpt,hints>", "k_batched") and returns how
+   many it filled. */
 int bmmc_profile_begin(void);
 int bmmc_profile_end(bmmc_kernel_stat_t* out, int max);
 

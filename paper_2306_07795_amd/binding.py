@@ -152,6 +152,7 @@ def lib():
         "bmmc_server_stats": (_i32, [_vp, P(ServerStats)]),
         "bmmc_server_now_ns": (_i64, []),
         "bmmc_server_reset_stats": (_i32, [_vp]),
+        "bmmc_serve_direct": (_i32, [P(Desc), P(_i64), _i32, _i32, P(ServerStats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -174,6 +175,7 @@ def exported_names():
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
         "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes", "bmmc_tune_lookup_batched",
         "bmmc_server_reset_stats", "bmmc_autotune_matrix", "bmmc_tune_clear_matrices",
+        "bmmc_serve_direct",
     ]
 
 
@@ -603,3 +605,15 @@ def bmmc_server_stats(handle) -> dict:
 
 def bmmc_server_now_ns() -> int:
     return int(lib().bmmc_server_now_ns())
+
+
+def bmmc_serve_direct(descs: "DescBatch", arrival_ns, streams: int = 4) -> dict:
+    """The unbatched baseline: each request k as its own bmmc_permute call at
+    arrival_ns[k] on stream k mod `streams` (one issuing thread per stream);
+    statistics as bmmc_server_stats."""
+    arr, keep, count = make_descs(descs)
+    arrivals = (_i64 * max(count, 1))(*[int(v) for v in arrival_ns])
+    s = ServerStats()
+    _check(lib().bmmc_serve_direct(arr, arrivals, count, streams, _c.byref(s)))
+    del keep
+    return {f: getattr(s, f) for f, _ in ServerStats._fields_ if f != "reserved"}

@@ -423,7 +423,7 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
         st = build_graph(bs, grid, hints, iters, second);
         if (st != BMMC_OK) return st;
     }
-    LaunchScope ls(ds, stream, "k_batched", moved);
+    LaunchScope ls(ds, stream, "k_batched", moved, false);
     if (o.use_graph >= 0) {
         e = hipGraphLaunch(bs->exec[graph_slot(hints, iters, second)], stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -615,7 +615,7 @@ extern "C" int bmmc_batch_launch(void* handle, void* stream_) {
     bool any = false;
     for (auto& ba : pb->arrays) any |= !ba.single;
     if (!any) return BMMC_OK;
-    LaunchScope ls(ds, stream, "k_batched", pb->moved);
+    LaunchScope ls(ds, stream, "k_batched", pb->moved, false);
     hipError_t e = pb->use_graph ? hipGraphLaunch(pb->exec, stream)
                                  : enqueue_phases_at((uint8_t*)pb->table, pb->L, pb->grid, pb->hints, pb->iters,
                                                      pb->second, stream);

@@ -5,6 +5,7 @@
 // output addresses are a per-tile scalar part XOR a per-thread part computed
 // once XOR a compile-time-selected per-iteration part, so the per-element cost
 // is one XOR and one shift whatever the matrix.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <type_traits>
 
@@ -33,6 +34,30 @@ union Vec16 {
 };
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Timing events for the next kernel this thread launches (profiling): the
+// runtime binds them to the kernel's own dispatch, so their interval is the
+// kernel's execution, with no marker commands between kernels.  A pair is
+// used by one launch only.
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void set_kernel_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool kernel_events_pending() { return t_ev_start != nullptr; }
+
+template <typename F, typename... Args>
+static void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    if (t_ev_start) {
+        hipEvent_t a = t_ev_start, b = t_ev_stop;
+        t_ev_start = t_ev_stop = nullptr;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
 
 // 16-byte global accesses; HINT bit 0 marks loads and bit 1 stores as
 // non-temporal (streamed, not kept in the caches).
@@ -260,7 +285,7 @@ hipError_t launch_tiled(int w, int nt, int iters, int hints, const void* in, voi
     const TiledEntry* e = find_tiled(w, nt, iters, hints);
     if (!e) return hipErrorInvalidValue;
     if (grid == 0 || grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(e->fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab, ntiles, xcds);
+    launch_k(e->fn, dim3(grid), dim3(nt), stream, (const u32x4*)in, (u32x4*)out, tab, ntiles, xcds);
     return hipGetLastError();
 }
 
@@ -420,8 +445,7 @@ hipError_t launch_tiled_net(int nt, int iters, int op, bool regs, const void* in
     for (const auto& e : kTiledNet) {
         if (e.nt != nt || e.iters != iters || e.op != op || e.regs != regs) continue;
         if (grid == 0 || grid > ntiles) grid = ntiles;
-        hipLaunchKernelGGL(e.fn, dim3(grid), dim3(nt), 0, stream, (const u32x4*)in, (u32x4*)out, tab, cols, ntiles,
-                           0u);
+        launch_k(e.fn, dim3(grid), dim3(nt), stream, (const u32x4*)in, (u32x4*)out, tab, cols, ntiles, 0u);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -460,9 +484,9 @@ hipError_t launch_cmp_direct(void* data, const DirectArgs& args, int op, hipStre
     const uint64_t pairs = 1ull << (args.n - 1);
     const uint32_t grid = (uint32_t)((pairs + 255) / 256);
     if (op == 1)
-        hipLaunchKernelGGL(k_cmp_direct<1>, dim3(grid), dim3(256), 0, stream, (uint32_t*)data, args);
+        launch_k(k_cmp_direct<1>, dim3(grid), dim3(256), stream, (uint32_t*)data, args);
     else if (op == 2)
-        hipLaunchKernelGGL(k_cmp_direct<2>, dim3(grid), dim3(256), 0, stream, (uint32_t*)data, args);
+        launch_k(k_cmp_direct<2>, dim3(grid), dim3(256), stream, (uint32_t*)data, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -514,9 +538,9 @@ hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs
 #define BMMC_NAIVE(WW)                                                                            \
     case WW:                                                                                      \
         if (vector)                                                                               \
-            hipLaunchKernelGGL((k_naive<WW, 16 / WW>), dim3(grid), dim3(256), 0, stream, i8, o8, args); \
+            launch_k(k_naive<WW, 16 / WW>, dim3(grid), dim3(256), stream, i8, o8, args);            \
         else                                                                                      \
-            hipLaunchKernelGGL((k_naive<WW, 1>), dim3(grid), dim3(256), 0, stream, i8, o8, args);       \
+            launch_k(k_naive<WW, 1>, dim3(grid), dim3(256), stream, i8, o8, args);                  \
         break;
     switch (w) {
         BMMC_NAIVE(1)
@@ -560,8 +584,7 @@ hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t stre
         const dim3 grid((uint32_t)((nvec + per - 1) / per));
         const u32x4* i4 = (const u32x4*)in;
         u32x4* o4 = (u32x4*)out;
-#define BMMC_COPY_H(V, H) \
-    hipLaunchKernelGGL((k_copy<V, H>), grid, dim3(256), 0, stream, i4, o4, nvec)
+#define BMMC_COPY_H(V, H) launch_k(k_copy<V, H>, grid, dim3(256), stream, i4, o4, nvec)
 #define BMMC_COPY(V)                            \
     case V:                                     \
         switch (hints) {                        \
@@ -651,7 +674,7 @@ k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ it
 hipError_t launch_batched(const BatchPass* passes, const BatchItem* items, const uint32_t* range,
                           uint32_t phase, uint32_t* head, uint32_t grid, int hints, int size, hipStream_t stream) {
 #define BMMC_BATCHED(H, NT, I) \
-    hipLaunchKernelGGL((k_batched<H, NT, I>), dim3(grid), dim3(NT), 0, stream, passes, items, range, phase, head)
+    launch_k(k_batched<H, NT, I>, dim3(grid), dim3(NT), stream, passes, items, range, phase, head)
 #define BMMC_BATCHED_H(NT, I)                  \
     switch (hints & 3) {                        \
         case 0: BMMC_BATCHED(0, NT, I); break; \

@@ -67,6 +67,13 @@ inline int batched_size(int asked) { return asked == 8 || asked == 16 || asked =
 inline int batched_threads(int size) { return size == 32 ? 1024 : size == 16 ? 512 : 256; }
 inline int batched_vectors(int size) { return size >= 16 ? 8 : size; }
 
+// Timing events bound to the next kernel launched by this thread through the
+// launchers above (hipExtLaunchKernel): their interval is that kernel's
+// execution.  A pair serves one launch; kernel_events_pending() tells whether
+// it is still unused.  Null events: plain launches.
+void set_kernel_events(hipEvent_t start, hipEvent_t stop);
+bool kernel_events_pending();
+
 // Clears `count` 32-bit words with a kernel (no memset nodes in graphs).
 hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream);
 

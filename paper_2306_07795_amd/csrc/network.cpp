@@ -120,7 +120,7 @@ int run_direct(DeviceState* ds, const std::vector<BitMat>& st, const void* in, v
     const size_t bytes = (size_t)4 << n;
     std::lock_guard<std::mutex> lk(ds->mu);
     {
-        LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
+        LaunchScope ls(ds, stream, "k_copy<4,0>", 2.0 * bytes);
         hipError_t e = launch_copy(in, out, bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "copy launch");
     }

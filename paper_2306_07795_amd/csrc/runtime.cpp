@@ -150,8 +150,14 @@ int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out) {
     return BMMC_OK;
 }
 
-LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes) : ds(d), stream(s) {
+LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes, bool one_kernel)
+    : ds(d), stream(s) {
     if (!ds->profiling) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return;
+    }
     ProfileEvent pe;
     pe.name = name;
     pe.bytes = bytes;
@@ -163,13 +169,28 @@ LaunchScope::LaunchScope(DeviceState* d, hipStream_t s, const char* name, double
             return;
         }
     }
-    hipEventRecord(pe.start, stream);
     ds->events.push_back(pe);
-    stop = pe.stop;
+    if (one_kernel) {
+        set_kernel_events(pe.start, pe.stop);
+        bound = true;
+    } else {
+        hipEventRecord(pe.start, stream);
+        stop = pe.stop;
+    }
 }
 
 LaunchScope::~LaunchScope() {
-    if (stop) hipEventRecord(stop, stream);
+    if (bound) {
+        if (kernel_events_pending()) {
+            // nothing was launched (an error before the launch): drop the entry
+            set_kernel_events(nullptr, nullptr);
+            ds->event_pool.push_back(ds->events.back().start);
+            ds->event_pool.push_back(ds->events.back().stop);
+            ds->events.pop_back();
+        }
+    } else if (stop) {
+        hipEventRecord(stop, stream);
+    }
 }
 
 // Library defaults of the general one-pass tile (BMMC_METHOD_AUTO and
@@ -302,7 +323,7 @@ int enqueue_plan(DeviceState* ds, const Plan& plan, const void* in, void* out, h
     const size_t bytes = ((size_t)1 << plan.n) * (size_t)plan.w;
     hipError_t e;
     if (plan.npass == 0) {
-        LaunchScope ls(ds, stream, "k_copy", 2.0 * bytes);
+        LaunchScope ls(ds, stream, "k_copy<4,0>", 2.0 * bytes);
         e = launch_copy(in, out, bytes, stream);
         return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
     }
@@ -539,7 +560,9 @@ int bmmc_copy_ex(const void* in, void* out, size_t bytes, int vpt, int hints, vo
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     std::lock_guard<std::mutex> lk(ds->mu);
-    LaunchScope ls(ds, (hipStream_t)stream, "k_copy", 2.0 * (double)bytes);
+    char name[32];
+    snprintf(name, sizeof(name), "k_copy<%d,%d>", vpt, hints);
+    LaunchScope ls(ds, (hipStream_t)stream, name, 2.0 * (double)bytes);
     hipError_t e = launch_copy(in, out, bytes, (hipStream_t)stream, vpt, hints);
     return e == hipSuccess ? BMMC_OK : hip_fail(e, "copy launch");
 }

@@ -61,14 +61,18 @@ int get_plan(DeviceState* ds, const uint64_t* rows, uint64_t c, int n, int w, co
 // Scratch of at least `bytes` for `stream` (caller holds ds->mu).
 int get_scratch(DeviceState* ds, hipStream_t stream, size_t bytes, void** out);
 
-// Timing of one launch when profiling is on (caller holds ds->mu): events
-// recorded on the stream right before (constructor) and after (destructor)
-// the work enqueued in the scope.
+// Timing of one launch when profiling is on (caller holds ds->mu).  With
+// one_kernel, the scope's events are bound to the one kernel launched in it
+// (its execution, nothing else); otherwise (a graph or several kernels) they
+// are recorded on the stream right before (constructor) and after
+// (destructor) the work enqueued in the scope.  Streams under capture are not
+// timed.
 struct LaunchScope {
     DeviceState* ds;
     hipStream_t stream;
     hipEvent_t stop = nullptr;
-    LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes);
+    bool bound = false;
+    LaunchScope(DeviceState* d, hipStream_t s, const char* name, double bytes, bool one_kernel = true);
     ~LaunchScope();
 };
 

@@ -216,6 +216,10 @@ void Server::plan_loop() {
             r->state = kFailed;
             r->done_ns = now_ns();
             rejected++;
+            if (opt.own_outputs == 2) {  // nobody will poll: forget the request
+                table.erase(r->ticket);
+                delete r;
+            }
             cv_done.notify_all();
             continue;
         }
@@ -347,6 +351,10 @@ void Server::dispatch_loop() {
                         in_use -= (int64_t)r->footprint;
                         r->footprint = 0;
                         rejected++;
+                        if (opt.own_outputs == 2) {
+                            table.erase(r->ticket);
+                            delete r;
+                        }
                     }
                     s.reqs.clear();
                     cv_done.notify_all();
@@ -380,6 +388,177 @@ void Server::dispatch_loop() {
 using namespace bmmc;
 
 extern "C" int64_t bmmc_server_now_ns(void) { return now_ns(); }
+
+namespace bmmc {
+namespace {
+
+// Latency percentiles and means of completed requests into *out.
+void fill_latency_stats(std::vector<double> v, bmmc_server_stats_t* out) {
+    if (v.empty()) return;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+        size_t k = (size_t)(p * (double)(v.size() - 1) + 0.5);
+        return v[std::min(k, v.size() - 1)];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_ms = sum / (double)v.size();
+    out->max_ms = v.back();
+}
+
+// One stream of the unbatched baseline: an issuing thread that calls
+// bmmc_permute for each of its requests at the request's arrival time and
+// records an event after it, and a waiting thread that stamps each request's
+// completion when its event has passed.
+struct DirectLane {
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> ring;  // event slots, reused in issue order
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::pair<int, size_t>> issued;  // (request, event slot)
+    size_t n_issued = 0, n_done = 0;
+    bool finished = false;
+};
+
+}  // namespace
+}  // namespace bmmc
+
+extern "C" int bmmc_serve_direct(const bmmc_desc_t* descs, const int64_t* arrival_ns, int count, int streams,
+                                 bmmc_server_stats_t* stats_out) {
+    if (!stats_out || count < 0 || (count > 0 && (!descs || !arrival_ns)))
+        return set_error(BMMC_ERR_ARG, "NULL argument");
+    if (streams <= 0) streams = 4;
+    if (streams > 16) return set_error(BMMC_ERR_ARG, "streams = %d above 16", streams);
+    // each request on its own (requests of one stream run in order, so they
+    // may share an output buffer)
+    for (int k = 0; k < count; k++) {
+        const bmmc_desc_t& d = descs[k];
+        if (d.n < 0 || d.n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "request %d: n = %d", k, d.n);
+        const int w = d.elem_bytes;
+        if (!(w == 1 || w == 2 || w == 4 || w == 8 || w == 16))
+            return set_error(BMMC_ERR_ARG, "request %d: elem_bytes = %d", k, w);
+        if (d.n > 0 && !d.A_rows) return set_error(BMMC_ERR_ARG, "request %d: A_rows is NULL", k);
+        const int s0 = validate_buffers(d.in, d.out, ((size_t)1 << d.n) * (size_t)w);
+        if (s0 != BMMC_OK) return set_error(s0, "request %d: %s", k, bmmc_last_error());
+    }
+    int st;
+    DeviceState* ds = device_state(&st);
+    if (!ds) return st;
+    const int device = ds->device;
+    constexpr size_t kRing = 1024;
+    std::vector<DirectLane> lanes(streams);
+    for (DirectLane& L : lanes) {
+        hipError_t e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        for (size_t i = 0; e == hipSuccess && i < kRing; i++) {
+            hipEvent_t ev = nullptr;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) L.ring.push_back(ev);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            for (DirectLane& M : lanes) {
+                for (hipEvent_t ev : M.ring) hipEventDestroy(ev);
+                if (M.stream) hipStreamDestroy(M.stream);
+            }
+            return set_error(BMMC_ERR_HIP, "baseline stream or event: %s", hipGetErrorString(e));
+        }
+    }
+    std::vector<int64_t> issued_ns(count, 0), done_ns(count, 0);
+    std::vector<int> status(count, BMMC_OK);
+    std::vector<std::thread> threads;
+    for (int li = 0; li < streams; li++) {
+        DirectLane* L = &lanes[li];
+        threads.emplace_back([&, L, li] {
+            hipSetDevice(device);
+            prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
+            for (int k = li; k < count; k += streams) {
+                // wait for the arrival: sleep while it is far, then spin
+                for (;;) {
+                    const int64_t left = arrival_ns[k] - now_ns();
+                    if (left <= 0) break;
+                    if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
+                }
+                size_t slot;
+                {
+                    std::unique_lock<std::mutex> lk(L->mu);
+                    L->cv.wait(lk, [&] { return L->n_issued - L->n_done < kRing; });
+                    slot = L->n_issued % kRing;
+                }
+                const bmmc_desc_t& d = descs[k];
+                int s2 = bmmc_permute(d.in, d.out, d.n, d.A_rows, d.c, d.elem_bytes, L->stream);
+                if (s2 == BMMC_OK && hipEventRecord(L->ring[slot], L->stream) != hipSuccess) s2 = BMMC_ERR_HIP;
+                issued_ns[k] = now_ns();
+                status[k] = s2;
+                std::lock_guard<std::mutex> lk(L->mu);
+                if (s2 == BMMC_OK) {
+                    L->issued.push_back({k, slot});
+                    L->n_issued++;
+                }
+                L->cv.notify_all();
+            }
+            std::lock_guard<std::mutex> lk(L->mu);
+            L->finished = true;
+            L->cv.notify_all();
+        });
+        threads.emplace_back([&, L] {
+            hipSetDevice(device);
+            for (;;) {
+                std::pair<int, size_t> job;
+                {
+                    std::unique_lock<std::mutex> lk(L->mu);
+                    L->cv.wait(lk, [&] { return !L->issued.empty() || L->finished; });
+                    if (L->issued.empty()) return;
+                    job = L->issued.front();
+                    L->issued.pop_front();
+                }
+                const hipError_t e = hipEventSynchronize(L->ring[job.second]);
+                done_ns[job.first] = now_ns();
+                if (e != hipSuccess) status[job.first] = BMMC_ERR_HIP;
+                std::lock_guard<std::mutex> lk(L->mu);
+                L->n_done++;
+                L->cv.notify_all();
+            }
+        });
+    }
+    for (auto& t : threads) t.join();
+    for (DirectLane& L : lanes) {
+        hipStreamSynchronize(L.stream);
+        for (hipEvent_t ev : L.ring) hipEventDestroy(ev);
+        hipStreamDestroy(L.stream);
+    }
+    bmmc_server_stats_t& out = *stats_out;
+    std::memset(&out, 0, sizeof(out));
+    out.submitted = count;
+    std::vector<double> lat;
+    int64_t first = -1, last = 0;
+    double plan = 0, run = 0;
+    for (int k = 0; k < count; k++) {
+        if (status[k] != BMMC_OK) {
+            out.rejected++;
+            continue;
+        }
+        out.completed++;
+        out.bytes_moved += 2.0 * (double)((size_t)1 << descs[k].n) * (double)descs[k].elem_bytes;
+        lat.push_back((double)(done_ns[k] - arrival_ns[k]) * 1e-6);
+        plan += (double)(issued_ns[k] - arrival_ns[k]) * 1e-6;
+        run += (double)(done_ns[k] - issued_ns[k]) * 1e-6;
+        if (first < 0 || arrival_ns[k] < first) first = arrival_ns[k];
+        last = std::max(last, done_ns[k]);
+    }
+    out.batches = out.completed;
+    out.mean_batch = out.completed ? 1.0 : 0.0;
+    out.busy_s = first >= 0 ? (double)(last - first) * 1e-9 : 0.0;
+    if (out.completed) {
+        out.mean_plan_ms = plan / (double)out.completed;
+        out.mean_run_ms = run / (double)out.completed;
+    }
+    fill_latency_stats(lat, &out);
+    for (int k = 0; k < count; k++)
+        if (status[k] != BMMC_OK) return set_error(status[k], "request %d failed: %s", k, bmmc_strerror(status[k]));
+    return BMMC_OK;
+}
 
 extern "C" int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out) {
     if (!opts || !handle_out) return set_error(BMMC_ERR_ARG, "opts/handle_out is NULL");
@@ -468,6 +647,11 @@ extern "C" int bmmc_server_submit(void* handle, const bmmc_desc_t* desc, int64_t
 extern "C" int bmmc_server_poll(void* handle, int64_t ticket, int wait, int64_t* done_ns, void** out_ptr) {
     Server* s = (Server*)handle;
     if (!s) return set_error(BMMC_ERR_ARG, "NULL handle");
+    // Requests of own_outputs == 2 are freed when they finish: waiting on one
+    // could outlive it, so such tickets can only be polled without waiting
+    // (BMMC_ERR_BUSY while pending, BMMC_ERR_NOTFOUND once finished).
+    if (wait && s->opt.own_outputs == 2)
+        return set_error(BMMC_ERR_ARG, "tickets of a server with own_outputs == 2 cannot be waited on");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->table.find(ticket);
     if (it == s->table.end()) return set_error(BMMC_ERR_NOTFOUND, "unknown ticket %lld", (long long)ticket);
@@ -531,20 +715,7 @@ extern "C" int bmmc_server_stats(void* handle, bmmc_server_stats_t* out) {
         out->mean_wait_ms = s->wait_ms / (double)s->completed;
         out->mean_run_ms = s->run_ms / (double)s->completed;
     }
-    std::vector<double> v = s->latencies_ms;
-    if (!v.empty()) {
-        std::sort(v.begin(), v.end());
-        auto pct = [&](double p) {
-            size_t k = (size_t)(p * (double)(v.size() - 1) + 0.5);
-            return v[std::min(k, v.size() - 1)];
-        };
-        out->p50_ms = pct(0.50);
-        out->p99_ms = pct(0.99);
-        double sum = 0;
-        for (double x : v) sum += x;
-        out->mean_ms = sum / (double)v.size();
-        out->max_ms = v.back();
-    }
+    fill_latency_stats(s->latencies_ms, out);
     return BMMC_OK;
 }
 

@@ -183,6 +183,8 @@ void random_bpc(int n, uint64_t seed, uint64_t* rows, uint64_t* c) {
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
+    // one pair per call of a flushed timing
+    std::vector<hipEvent_t> as, bs;
     Timer() {
         hipEventCreate(&a);
         hipEventCreate(&b);
@@ -190,7 +192,49 @@ struct Timer {
     ~Timer() {
         hipEventDestroy(a);
         hipEventDestroy(b);
+        for (hipEvent_t e : as) hipEventDestroy(e);
+        for (hipEvent_t e : bs) hipEventDestroy(e);
     }
+    bool reserve(size_t k) {
+        while (as.size() < k) {
+            hipEvent_t x = nullptr, y = nullptr;
+            if (hipEventCreate(&x) != hipSuccess) return false;
+            if (hipEventCreate(&y) != hipSuccess) {
+                hipEventDestroy(x);
+                return false;
+            }
+            as.push_back(x);
+            bs.push_back(y);
+        }
+        return true;
+    }
+};
+
+// The cache state calls are timed in from 64 MiB on: before each timed call,
+// a copy of kFlushBytes between two other buffers (outside the timed
+// interval) leaves the L2 caches and the 256 MB last-level cache holding
+// another array's lines, many of them dirty, as when a call follows
+// unrelated work.  Below 64 MiB calls are timed back to back (graph
+// replays), the state of an array that stays in the caches between uses.
+constexpr size_t kFlushBytes = (size_t)512 << 20;
+constexpr size_t kFlushFrom = (size_t)64 << 20;
+
+struct FlushBufs {
+    void* a = nullptr;
+    void* b = nullptr;
+    ~FlushBufs() {
+        if (a) hipFree(a);
+        if (b) hipFree(b);
+    }
+    // false when the buffers cannot be allocated
+    bool make(hipStream_t stream) {
+        if (hipMalloc(&a, kFlushBytes) != hipSuccess || hipMalloc(&b, kFlushBytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return hipMemsetAsync(a, 0x3c, kFlushBytes, stream) == hipSuccess;
+    }
+    hipError_t flush(hipStream_t stream) const { return launch_copy(a, b, kFlushBytes, stream, 1, 0); }
 };
 
 }  // namespace
@@ -280,12 +324,34 @@ struct TuneMatrix {
 // below 64 MiB run for a few microseconds, less than the host takes to
 // issue a call: their `reps` calls are captured into a graph (on `cap`,
 // where a first call outside the capture has made any scratch) and the
-// graph's replay is timed, so that device time is what is compared.
+// graph's replay is timed, so that device time is what is compared.  From
+// 64 MiB on, with `fl`, every call is timed on its own after a cache flush.
 double time_options(int n, int elem_bytes, const std::vector<TuneMatrix>& mats, const bmmc_options_t& o,
-                    const void* in, void* out, hipStream_t stream, hipStream_t cap, int reps, Timer& tm) {
+                    const void* in, void* out, hipStream_t stream, hipStream_t cap, int reps, Timer& tm,
+                    const FlushBufs* fl = nullptr) {
     double total = 0;
-    const bool graph = cap && ((size_t)1 << n) * (size_t)elem_bytes < ((size_t)64 << 20);
+    const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
+    const bool graph = cap && bytes < kFlushFrom;
     for (const TuneMatrix& m : mats) {
+        if (!graph && fl && fl->a && bytes >= kFlushFrom) {
+            if (bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream) != BMMC_OK) return -1;
+            if (!tm.reserve((size_t)reps)) return -1;
+            for (int r = 0; r < reps; r++) {
+                if (fl->flush(stream) != hipSuccess) return -1;
+                hipEventRecord(tm.as[r], stream);
+                bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream);
+                hipEventRecord(tm.bs[r], stream);
+            }
+            if (hipEventSynchronize(tm.bs[reps - 1]) != hipSuccess) return -1;
+            double sum = 0;
+            for (int r = 0; r < reps; r++) {
+                float ms = 0;
+                hipEventElapsedTime(&ms, tm.as[r], tm.bs[r]);
+                sum += ms;
+            }
+            total += sum / reps;
+            continue;
+        }
         if (!graph) {
             if (bmmc_permute_ex(in, out, n, m.rows, m.c, elem_bytes, &o, stream) != BMMC_OK) return -1;
             hipEventRecord(tm.a, stream);
@@ -354,7 +420,7 @@ void drop_capture_stream(DeviceState* ds, hipStream_t cap) {
 // Returns the fastest options and their time per matrix.
 void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with_tiled,
                    const std::vector<TuneMatrix>& mats, const void* in, void* out, hipStream_t stream, int reps,
-                   bmmc_options_t* bo, double* best) {
+                   const FlushBufs* fl, bmmc_options_t* bo, double* best) {
     static const int kShapes[][2] = {{256, 2}, {512, 2}, {256, 4}, {256, 8}, {512, 4}, {512, 8}, {1024, 4}, {256, 16}};
     // tile orders: plain, and neighbouring tiles writing neighbouring runs
     // for the 7 lowest tile-index bits (best for most large arrays)
@@ -373,7 +439,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
         return ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
     };
     auto run = [&](const bmmc_options_t& o) {
-        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm);
+        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm, fl);
         if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
     };
     {
@@ -461,7 +527,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
             const double per_call = timed[i].first / (double)mats.size();
             int r = (int)std::ceil(5.0 / (per_call > 1e-4 ? per_call : 1e-4));
             r = std::max(reps * 2, std::min(r, 200));
-            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm);
+            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm, fl);
             if (t > 0 && t < again[i]) again[i] = t;
         }
     for (size_t i = 0; i < keep; i++)
@@ -497,6 +563,12 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         return set_error(BMMC_ERR_NOMEM, "autotune buffers of %zu bytes", bytes);
     }
     hipMemsetAsync(in, 0x5a, bytes, stream);
+    FlushBufs fl;
+    if (bytes >= kFlushFrom && !fl.make(stream)) {
+        hipFree(in);
+        hipFree(out);
+        return set_error(BMMC_ERR_NOMEM, "autotune cache-flush buffers of 2 x %zu bytes", kFlushBytes);
+    }
     bmmc_options_t bo[2];
     double best[2];
     for (int cls = 0; cls < 2; cls++) {
@@ -522,7 +594,7 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         }
         // a tiled matrix is one tiled pass by every method but the general tile
         tune_matrices(ds, n, elem_bytes, method, method == BMMC_METHOD_AUTO && cls == 0, mats, in, out, stream,
-                      reps, &bo[cls], &best[cls]);
+                      reps, &fl, &bo[cls], &best[cls]);
     }
     hipStreamSynchronize(stream);
     hipFree(in);
@@ -690,11 +762,14 @@ extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint
             }
         }
     }
+    FlushBufs fl;
+    if (bytes >= kFlushFrom && !fl.make(stream))
+        return set_error(BMMC_ERR_NOMEM, "autotune cache-flush buffers of 2 x %zu bytes", kFlushBytes);
     Timer tm;
     hipStream_t cap = make_capture_stream();
     std::vector<std::pair<double, bmmc_options_t>> timed;
     for (const bmmc_options_t& o : cands) {
-        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm);
+        const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm, &fl);
         if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
     }
     std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
@@ -705,7 +780,7 @@ extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint
             const double per_call = timed[i].first;
             int r = (int)std::ceil(5.0 / (per_call > 1e-4 ? per_call : 1e-4));
             r = std::max(reps * 2, std::min(r, 200));
-            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm);
+            const double t = time_options(n, elem_bytes, mats, timed[i].second, in, out, stream, cap, r, tm, &fl);
             if (t > 0 && t < again[i]) again[i] = t;
         }
     drop_capture_stream(ds, cap);

@@ -86,17 +86,36 @@ def data(n: int, w: int, seed: int, chunk: int = 1 << 22) -> np.ndarray:
     if w == 16:
         out = np.empty((size, 2), dtype=np.uint64)
         flat = out.reshape(-1)
-        for a in range(0, 2 * size, chunk):
+
+        def fill(a):
             m = min(chunk, 2 * size - a)
             flat[a:a + m] = splitmix64_array(s, m, a)
+        _each_chunk(fill, 2 * size, chunk)
         return out
     if w not in _DTYPES:
         raise ValueError("element width must be 1, 2, 4, 8 or 16 bytes")
     out = np.empty(size, dtype=_DTYPES[w])
-    for a in range(0, size, chunk):
+
+    def fill(a):
         m = min(chunk, size - a)
         out[a:a + m] = splitmix64_array(s, m, a).astype(_DTYPES[w])
+    _each_chunk(fill, size, chunk)
     return out
+
+
+def _each_chunk(fill, total: int, chunk: int):
+    """fill(a) for a = 0, chunk, 2 chunk, ... < total; large arrays on a few
+    threads (numpy's elementwise work releases the GIL; every chunk depends
+    only on its own offsets, so the result is the same)."""
+    starts = range(0, total, chunk)
+    if len(starts) <= 2:
+        for a in starts:
+            fill(a)
+        return
+    import concurrent.futures as cf
+    import os
+    with cf.ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
+        list(ex.map(fill, starts))
 
 
 def iota(n: int, w: int) -> np.ndarray:

@@ -101,32 +101,56 @@ def test_graph_replays_with_fresh_data():
         check_all(arrays)
 
 
-@pytest.mark.parametrize("iters", [4, 8, 16, 32])
-@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
-def test_batch_of_1024_like_the_workload(method, iters):
-    """1024 arrays, n uniform in [10, 22], int32, each with its own A and c
-    (the batched workload's shape); every array checked on sampled outputs
-    and the smallest hundred in full."""
+def workload_batch():
+    """The benchmark's batch: 1024 arrays, n uniform in [10, 22], int32, each
+    with its own A and c (the benchmark's matrix seeds) and data of its own."""
     sizes = gen.batched_sizes(1024, 0, 10, 22)
     arrays = []
     for k, n in enumerate(sizes):
-        rows, c = gen.random_bmmc(n, k)
+        rows, c = gen.random_bmmc(n, 1_000_003 + k)
         a = gen.data(n, 4, k)
         arrays.append({"n": n, "w": 4, "rows": rows, "c": c, "a": a,
                        "x": G.to_device(a), "y": G.empty_like_bytes(a)})
+    return arrays
+
+
+@pytest.mark.parametrize("iters", [4, 8, 16, 32])
+@pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
+def test_batch_of_1024_like_the_workload(method, iters):
+    """The batched workload in every tile size and both methods: every one
+    of the 1024 arrays compared in full."""
+    arrays = workload_batch()
     B.bmmc_permute_batched(items(arrays), G.stream(), {"method": method, "iters": iters})
     G.sync()
-    rng = np.random.default_rng(0)
-    order = sorted(range(len(arrays)), key=lambda k: arrays[k]["n"])
-    for rank, k in enumerate(order):
-        ar = arrays[k]
-        got = G.to_host(ar["y"], ar["a"])
-        if rank < 100:
-            assert np.array_equal(got, O.permute(ar["a"], ar["n"], ar["rows"], ar["c"]))
-        else:
-            xs = rng.integers(0, 1 << ar["n"], size=512, dtype=np.uint64)
-            ys = O.apply_many(ar["rows"], ar["c"], ar["n"], xs).astype(np.int64)
-            assert np.array_equal(got[ys], ar["a"][xs.astype(np.int64)]), f"array {k}"
+    check_all(arrays)
+
+
+def test_batch_of_1024_as_the_benchmark_runs_it():
+    """The benchmark's calls on its batch: a resident batch with the tuned
+    options of the tuning file (replayed twice with new data in between) and
+    the one-shot batched call without options; every array in full."""
+    arrays = workload_batch()
+    tuned = B.bmmc_tune_lookup_batched(items(arrays))
+    assert tuned is not None, "the tuning file has an entry for the benchmark's batch"
+    pb = B.bmmc_batch_create(items(arrays), tuned)
+    try:
+        for rep in range(2):
+            if rep:
+                for k, ar in enumerate(arrays):
+                    ar["a"] = gen.data(ar["n"], 4, 5000 + k)
+                    ar["x"].copy_(torch.from_numpy(ar["a"].view(np.uint8)).to(G.dev()))
+                    ar["y"].zero_()
+                torch.cuda.synchronize()
+            pb.launch(G.stream())
+            G.sync()
+            check_all(arrays)
+    finally:
+        pb.close()
+    for ar in arrays:
+        ar["y"].zero_()
+    B.bmmc_permute_batched(items(arrays), G.stream())
+    G.sync()
+    check_all(arrays)
 
 
 def test_batched_equals_separate_calls():
