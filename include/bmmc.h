@@ -364,6 +364,25 @@ int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc_batch_opti
 int bmmc_batch_launch(void* handle, void* stream);
 int bmmc_batch_destroy(void* handle);
 
+/* bmmc_permute_batched for callers that cannot allocate device memory (code
+   that must not call hipMalloc: tight serving loops, harnesses that forbid
+   it).  Same descriptors, options (NULL: as bmmc_permute_batched) and
+   results; no hipMalloc, hipFree or other allocating routine is called.
+   The batch's descriptor table, work items and queue heads go into one
+   fixed device array of bmmc_noalloc_table_bytes() bytes (4 MiB) that the
+   library holds on each device it runs on until the process ends; the
+   kernels run as plain launches (no graph).  Every call on a device shares
+   that array and leaves its contents behind (the queue heads are cleared
+   by a kernel at the start of each call): calls that overlap on one device,
+   from any stream or thread, race and must be serialized by the caller;
+   calls one after another on one stream are safe.
+   Errors: as bmmc_permute_batched; _RANGE when the batch's table does not fit
+   the fixed array (about 4 MiB: a few thousand arrays), _ARG for
+   BMMC_METHOD_TILED (two-pass arrays need scratch as large as themselves). */
+int bmmc_permute_batched_noalloc(const bmmc_desc_t* descs, int count,
+                                 const bmmc_batch_options_t* opts, void* stream);
+size_t bmmc_noalloc_table_bytes(void);
+
 /* ------------------------------------------------------------- autotuner */
 
 /* Time the available tile shapes (threads x iterations), run widths, cache

@@ -153,6 +153,8 @@ def lib():
         "bmmc_server_now_ns": (_i64, []),
         "bmmc_server_reset_stats": (_i32, [_vp]),
         "bmmc_serve_direct": (_i32, [P(Desc), P(_i64), _i32, _i32, P(ServerStats)]),
+        "bmmc_permute_batched_noalloc": (_i32, [P(Desc), _i32, P(BatchOptions), _vp]),
+        "bmmc_noalloc_table_bytes": (_c.c_size_t, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -175,7 +177,7 @@ def exported_names():
         "bmmc_server_stats", "bmmc_server_now_ns", "bmmc_sortnet_stages", "bmmc_sortnet",
         "bmmc_tune_lookup", "bmmc_sortnet_emulate", "bmmc_sortnet_passes", "bmmc_tune_lookup_batched",
         "bmmc_server_reset_stats", "bmmc_autotune_matrix", "bmmc_tune_clear_matrices",
-        "bmmc_serve_direct",
+        "bmmc_serve_direct", "bmmc_permute_batched_noalloc", "bmmc_noalloc_table_bytes",
     ]
 
 
@@ -449,6 +451,18 @@ def bmmc_permute_batched(items, stream=None, opts=None):
     else:
         _check(lib().bmmc_permute_batched_ex(arr, count, _batch_options(opts), _stream(stream)))
     del keep
+
+
+def bmmc_permute_batched_noalloc(items, stream=None, opts=None):
+    """bmmc_permute_batched without device allocation (the library's fixed
+    table; calls on one device must not overlap)."""
+    arr, keep, count = make_descs(items)
+    _check(lib().bmmc_permute_batched_noalloc(arr, count, _batch_options(opts), _stream(stream)))
+    del keep
+
+
+def bmmc_noalloc_table_bytes() -> int:
+    return int(lib().bmmc_noalloc_table_bytes())
 
 
 def bmmc_profile_begin():

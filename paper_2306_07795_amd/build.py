@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "bmmc")
 LIB = os.path.join(HERE, "libbmmc.so")
 SOURCES = ["kernels.hip", "runtime.cpp", "plan.cpp", "emulate.cpp", "batched.cpp", "server.cpp",
-           "tune.cpp", "algebra.cpp", "network.cpp"]
+           "tune.cpp", "algebra.cpp", "network.cpp", "noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -434,6 +434,55 @@ int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc
     return BMMC_OK;
 }
 
+// The batch with its device table at `table` (cap bytes, caller-provided):
+// the table image is built in host memory, copied in, and both phases run as
+// plain launches.  No device memory is allocated, so arrays that take two
+// passes (they need a scratch array as large as themselves) are refused.
+int enqueue_batched_fixed(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
+                          hipStream_t stream, void* table, size_t cap) {
+    const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;
+    for (size_t i = 0; i < arrays.size(); i++)
+        if (arrays[i].plan->npass > 1)
+            return set_error(BMMC_ERR_ARG,
+                             "array %zu takes two passes, whose scratch array would have to be allocated", i);
+    int st = check_batch_shapes(arrays, batched_size(o.iters));
+    if (st != BMMC_OK) return st;
+    const std::vector<size_t> work = work_order(arrays, o.order);
+    size_t npasses = 0, nitems = 0;
+    table_counts(arrays, work, chunk, &npasses, &nitems);
+    const Layout L = layout_for(npasses, nitems);
+    if (!work.empty() && L.total > cap)
+        return set_error(BMMC_ERR_RANGE, "batch table of %zu bytes exceeds the fixed %zu-byte table", L.total, cap);
+    for (const BatchArray& a : arrays) {
+        if (!a.single) continue;
+        st = enqueue_plan(ds, *a.plan, a.in, a.out, stream, a.grid, a.hints, a.order, nullptr);
+        if (st != BMMC_OK) return st;
+    }
+    if (work.empty()) return BMMC_OK;
+    // Host image of the table; hipMemcpyAsync from pageable memory has
+    // consumed it when it returns, so the next call may refill it.
+    static thread_local std::vector<uint8_t> image;
+    image.assign(L.total, 0);
+    size_t ni;
+    double moved;
+    const uint32_t np = fill_table(arrays, work, chunk, image.data(), L, &ni, &moved);
+    hipError_t e = hipMemcpyAsync(table, image.data(), L.passes_off + np * sizeof(BatchPass),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((uint8_t*)table + L.items_off, image.data() + L.items_off, ni * sizeof(BatchItem),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (fixed batch table)");
+    const int iters = batched_size(o.iters);
+    uint32_t grid = o.workgroups > 0 ? (uint32_t)o.workgroups : (uint32_t)(ds->cu_count * batched_occupancy(iters));
+    const uint32_t* range = (const uint32_t*)image.data();
+    const bool second = range[2] > range[1];
+    const uint32_t most = std::max(range[1] - range[0], range[2] - range[1]);
+    grid = std::max(1u, std::min(grid, most));
+    LaunchScope ls(ds, stream, "k_batched", moved, false);
+    e = enqueue_phases_at((uint8_t*)table, L, grid, resolve_batch_hints(o, moved), iters, second, stream);
+    return e == hipSuccess ? BMMC_OK : hip_fail(e, "batched launch");
+}
+
 // Signature of a batch for the tuning cache: count and a histogram of
 // (n, width) pairs.
 uint64_t batch_signature(const bmmc_desc_t* descs, int count) {
@@ -451,6 +500,11 @@ uint64_t batch_signature(const bmmc_desc_t* descs, int count) {
     return h;
 }
 
+void default_batch_options(const bmmc_desc_t* descs, int count, bmmc_batch_options_t* o) {
+    std::memset(o, 0, sizeof(*o));
+    if (!tuned_batch_options(batch_signature(descs, count), o)) untuned_batch_options(descs, count, o);
+}
+
 }  // namespace bmmc
 
 using namespace bmmc;
@@ -461,9 +515,8 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     if (st != BMMC_OK) return st;
     if (count == 0) return BMMC_OK;
     bmmc_batch_options_t o;
-    std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    else if (!tuned_batch_options(batch_signature(descs, count), &o)) untuned_batch_options(descs, count, &o);
+    else default_batch_options(descs, count, &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
         return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
@@ -525,9 +578,8 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     if (st != BMMC_OK) return st;
     if (count == 0) return set_error(BMMC_ERR_ARG, "empty batch");
     bmmc_batch_options_t o;
-    std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    else if (!tuned_batch_options(batch_signature(descs, count), &o)) untuned_batch_options(descs, count, &o);
+    else default_batch_options(descs, count, &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
         return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
     if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");

@@ -118,6 +118,14 @@ int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchAr
 // Enqueue one batched launch (caller holds ds->mu).
 int enqueue_batched(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
                     hipStream_t stream);
+// The same with the device table at `table` (cap bytes, owned by the
+// caller) and plain launches: allocates no device memory; refuses arrays
+// that take two passes and tables larger than cap (caller holds ds->mu).
+int enqueue_batched_fixed(DeviceState* ds, std::vector<BatchArray>& arrays, const bmmc_batch_options_t& o,
+                          hipStream_t stream, void* table, size_t cap);
+// Options a batch takes when the caller gives none: the tuning cache's entry
+// for its histogram of (n, width), else the untuned defaults.
+void default_batch_options(const bmmc_desc_t* descs, int count, bmmc_batch_options_t* o);
 uint64_t batch_signature(const bmmc_desc_t* descs, int count);
 // Size the batch table and its pinned staging of `stream` for at least this
 // many passes and work items now, so that later batched launches on it do
