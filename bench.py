@@ -551,7 +551,7 @@ def bench_served(rate=20000.0, seconds=10.0, warm_s=1.0, budget=64 << 30, seed=0
         B.bmmc_server_drain(srv)
         B.bmmc_server_reset_stats(srv)
         descs = marshal(reqs, mats)
-        lead = 1.0
+        lead = 5.0
         start = B.bmmc_server_now_ns() + int(lead * 1e9)
         B.bmmc_server_submit_many(srv, descs, [start + int(r["arrival"] * 1e9) for r in reqs])
         submit_s = (B.bmmc_server_now_ns() - start) * 1e-9 + lead

@@ -431,10 +431,14 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
     Timer tm;
     hipStream_t cap = make_capture_stream();
     const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
-    // non-temporal stores (2) or loads and stores (3) beyond the last-level
-    // cache, none (4) or stores only below it
-    const int hint_set[2][2] = {{4, 2}, {2, 3}};
-    const int* hints_of = hint_set[bytes > ((size_t)8 << 20) ? 1 : 0];
+    // cache hints (bit 0 non-temporal loads, bit 1 non-temporal stores, 4
+    // none): up to 8 MiB none or stores, up to 64 MiB stores or both (these
+    // sizes are timed warm, in graph replays); from 64 MiB on, where each
+    // call is timed after a cache flush, all four
+    const int hint_set[3][4] = {{4, 2, 0, 0}, {2, 3, 0, 0}, {1, 3, 2, 4}};
+    const int hk = bytes >= kFlushFrom ? 2 : bytes > ((size_t)8 << 20) ? 1 : 0;
+    const int* hints_of = hint_set[hk];
+    const int nh = hk == 2 ? 4 : 2;
     auto persistent_grid = [&](const bmmc_options_t& o) {
         return ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
     };
@@ -465,7 +469,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
                 for (int m = 0; m < (with_tiled ? 2 : 1); m++) {
                     const bool two = m == 1 || method == BMMC_METHOD_TILED;
                     // two-pass plans also with the scratch kept in the caches
-                    for (int hi = 0; hi < (two ? 4 : 2); hi++) {
+                    for (int hi = 0; hi < (two ? 2 * nh : nh); hi++) {
                         for (int order : kStage1Orders) {
                             for (int g = 0; g < 2; g++) {
                                 bmmc_options_t o;
@@ -478,7 +482,7 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
                                 o.threads = ks.nt;
                                 o.iters = ks.iters;
                                 o.swizzle = 1;
-                                o.hints = hints_of[hi & 1] | (hi >= 2 ? 8 : 0);
+                                o.hints = hints_of[hi % nh] | (hi >= nh ? 8 : 0);
                                 o.tile_order = order;
                                 o.grid = g == 0 ? -1 : persistent_grid(o);
                                 run(o);
