@@ -781,9 +781,11 @@ def main():
         print(json.dumps({"workload": "served load sweep: server (4 streams) against per-request launches on "
                                       "1 and 4 streams, same Poisson requests", "table": rows}), flush=True)
         return
+    # entry of profiles/traffic.json: the workload, and the method unless it is the default
+    traffic_key = args.workload + ("" if args.method == "auto" else "_" + args.method)
     if args.traffic_from:
         n, w = WORKLOADS[args.workload][:2]
-        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w, args.workload),
+        print(json.dumps(write_traffic(args.traffic_from[0], args.traffic_from[1], (1 << n) * w, traffic_key),
                          indent=1))
         return
 
@@ -842,14 +844,15 @@ def main():
 
     # timed region: exactly `steps` permutations, each right after a cache
     # flush (outside the timed interval); HIP events on the stream around
-    # each step.  The library's profiling binds a second pair of events to
-    # every kernel it launches, which gives each launch's own duration.
+    # each step.  Then the same steps again with the library's profiling on:
+    # it binds a second pair of events to every kernel it launches, which
+    # gives each launch's own duration (the roofline), but its bookkeeping
+    # would lengthen the steps, so it stays out of the timed steps.
     flush = Flusher(dev)
     for _ in range(args.warmup):
         flush(stream)
         step()
     torch.cuda.synchronize()
-    B.bmmc_profile_begin()
     evs = []
     for _ in range(args.steps):
         flush(stream)
@@ -858,6 +861,11 @@ def main():
         step()
         eb.record(stream)
         evs.append((ea, eb))
+    torch.cuda.synchronize()
+    B.bmmc_profile_begin()
+    for _ in range(args.steps):
+        flush(stream)
+        step()
     torch.cuda.synchronize()
     kstats = B.bmmc_profile_end()
     step_ms = [ea.elapsed_time(eb) for ea, eb in evs]
@@ -909,14 +917,15 @@ def main():
     per_launch_ms = d["total_ms"] / d["launches"]
     launch_bytes = d["bytes"] / d["launches"]
     achieved = launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    tbytes = traffic_for(args.workload, dname)
+    tbytes = traffic_for(traffic_key, dname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 # HBM bytes per launch from the rocprofv3 counters, as a rate over the same launch time
                 "traffic": None if tbytes is None else round(tbytes / (per_launch_ms * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": tbytes,
                 "kernel": dname, "launches": d["launches"], "mean_launch_ms": round(per_launch_ms, 5),
-                "launch_time_from": "events bound to each launch of the timed steps (hipExtLaunchKernel)",
+                "launch_time_from": "events bound to each launch (hipExtLaunchKernel) of a second, profiled "
+                                    "run of the timed steps",
                 "cache_state": "flushed before every step",
                 "bytes_per_launch": launch_bytes}
 
