@@ -633,172 +633,41 @@ hipError_t launch_zero(uint32_t* p, uint32_t count, hipStream_t stream) {
 // vectors x 16 bytes (256 x 4, 256 x 8, 512 x 8 or 1024 x 8: 16, 32, 64 or
 // 128 KiB).
 // Thread 0 fetches the next item's index as soon as the current item
-// starts, so the atomic's latency overlaps the current item's tiles.  The
-// tiles of all items form one pipelined stream per work-group: the loads of
-// the next tile -- the item's next tile, or the first tile of the next item,
-// of another array and possibly another width -- are issued right after the
-// current tile is staged in LDS, and are in flight while it is written out.
+// starts, so the atomic's latency overlaps the current item's tiles.
 // ---------------------------------------------------------------------------
-template <int NT, int ITERS>
-struct BatchCursor {
-    static constexpr int LT = ilog2(NT);
-    static constexpr int LI = ilog2(ITERS);
-    const PassTables* P;
-    const g_u32x4* in;
-    g_u32x4* out;
-    uint32_t w;               // element bytes: 4, 8 or 16
-    uint32_t lv;              // log2 of the elements in a 16-byte vector
-    uint32_t xt, ft, yt, gt;  // per-thread parts (TileCtx::init with a run-time width)
-    uint32_t vlim;            // valid vector slots
-    uint32_t tile, end;       // current tile, end of the item's range
-
-    __device__ __forceinline__ void start(const BatchPass& bp, const BatchItem& item, uint32_t tid) {
-        P = &bp.tab;
-        in = (const g_u32x4*)bp.in;
-        out = (g_u32x4*)bp.out;
-        w = bp.w;
-        lv = w == 4 ? 2u : w == 8 ? 1u : 0u;
-        xt = ft = yt = gt = 0;
-#pragma unroll
-        for (int k = 0; k < LT; k++) {
-            const uint32_t m = 0u - ((tid >> k) & 1u);
-            xt ^= P->X[lv + k] & m;
-            ft ^= P->F[lv + k] & m;
-            yt ^= P->Y[lv + k] & m;
-            gt ^= P->G[lv + k] & m;
-        }
-        vlim = 1u << (P->d - lv);
-        tile = item.tile_begin;
-        end = item.tile_end;
-    }
-
-    struct Parts {
-        uint32_t r, yb, gx;
-    };
-    __device__ __forceinline__ Parts parts() const {
-        Parts p{0u, P->c_hi, P->c_lds};
-        for (uint32_t m = tile; m; m &= m - 1) {
-            const uint32_t j = __builtin_ctz(m);
-            p.r ^= P->tb[j][0];
-            p.yb ^= P->tb[j][1];
-            p.gx ^= P->tb[j][2];
-        }
-        return p;
-    }
-
-    // Loads do not depend on the width beyond the vector index x >> lv.
-    template <int HINT>
-    __device__ __forceinline__ void load(uint32_t r, u32x4 (&buf)[ITERS], uint32_t tid) const {
-#pragma unroll
-        for (int it = 0; it < ITERS; it++) {
-            if ((uint32_t)(it * NT) + tid < vlim) {
-                uint32_t x = r ^ xt;
-#pragma unroll
-                for (int k = 0; k < LI; k++)
-                    if ((it >> k) & 1) x ^= P->X[lv + LT + k];
-                buf[it] = ld16<HINT>(in + (x >> lv));
-            }
-        }
-    }
-
-    template <int W>
-    __device__ __forceinline__ void to_lds(uint8_t* lds_bytes, const u32x4 (&buf)[ITERS], uint32_t tid) const {
-        using E = typename ElemT<W>::T;
-        constexpr int LV = ilog2(16 / W);
-        E* lds = (E*)lds_bytes;
-#pragma unroll
-        for (int it = 0; it < ITERS; it++) {
-            if ((uint32_t)(it * NT) + tid < vlim) {
-                const uint32_t f = ft ^ lin_const<LV + LT, LI>(P->F, it);
-                Vec16<W> v;
-                v.v = buf[it];
-#pragma unroll
-                for (int e = 0; e < 16 / W; e++) lds[f ^ lin_const<0, LV>(P->F, e)] = v.e[e];
-            }
-        }
-    }
-
-    template <int W, int HINT>
-    __device__ __forceinline__ void store(const uint8_t* lds_bytes, const Parts& pt, uint32_t tid) const {
-        using E = typename ElemT<W>::T;
-        constexpr int LV = ilog2(16 / W);
-        const E* lds = (const E*)lds_bytes;
-#pragma unroll
-        for (int it = 0; it < ITERS; it++) {
-            if ((uint32_t)(it * NT) + tid < vlim) {
-                const uint32_t g = gt ^ pt.gx ^ lin_const<LV + LT, LI>(P->G, it);
-                Vec16<W> o;
-#pragma unroll
-                for (int e = 0; e < 16 / W; e++) o.e[e] = lds[g ^ lin_const<0, LV>(P->G, e)];
-                const uint32_t y = pt.yb ^ yt ^ lin_const<LV + LT, LI>(P->Y, it);
-                st16<HINT>(out + (y >> LV), o.v);
-            }
-        }
-    }
-};
+template <int W, int HINT, int NT, int ITERS>
+__device__ __forceinline__ void batch_tiles(const BatchPass& bp, uint32_t t0, uint32_t t1,
+                                            uint8_t* lds_bytes, uint32_t tid) {
+    using C = TileCtx<W, NT, ITERS, HINT>;
+    C ctx;
+    ctx.init(bp.tab, tid);
+    ctx.run_tiles(bp.tab, (const g_u32x4*)bp.in, (g_u32x4*)bp.out, (typename C::E*)lds_bytes, t0, t1, 1, tid);
+}
 
 // range[phase] .. range[phase + 1] are this launch's items.
 template <int HINT, int NT, int ITERS>
 __global__ void __launch_bounds__(NT)
 k_batched(const BatchPass* __restrict__ passes, const BatchItem* __restrict__ items,
           const uint32_t* __restrict__ range, uint32_t phase, uint32_t* head) {
-    using Cur = BatchCursor<NT, ITERS>;
     __shared__ __attribute__((aligned(16))) uint8_t lds[NT * ITERS * 16];
     __shared__ uint32_t s_next;
     const uint32_t tid = threadIdx.x;
     const uint32_t first = range[phase], last = range[phase + 1];
     if (tid == 0) s_next = first + __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    uint32_t idx = __builtin_amdgcn_readfirstlane(s_next);
-    __syncthreads();  // every thread has read s_next before it is rewritten
-    if (idx >= last) return;
-    // s_next always holds the item after the one being worked on
-    if (tid == 0) s_next = first + __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    Cur cur;
-    {
-        const BatchItem item = items[idx];
-        cur.start(passes[item.pass], item, tid);
-    }
-    typename Cur::Parts pc = cur.parts();
-    u32x4 buf[ITERS];
-    cur.template load<HINT>(pc.r, buf, tid);
     for (;;) {
-        switch (cur.w) {
-            case 4: cur.template to_lds<4>(lds, buf, tid); break;
-            case 8: cur.template to_lds<8>(lds, buf, tid); break;
-            default: cur.template to_lds<16>(lds, buf, tid); break;
+        const uint32_t idx = s_next;
+        __syncthreads();  // every thread has read s_next before it is rewritten
+        if (idx >= last) break;
+        if (tid == 0) s_next = first + __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const BatchItem item = items[idx];
+        const BatchPass& bp = passes[item.pass];
+        switch (bp.w) {
+            case 4: batch_tiles<4, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            case 8: batch_tiles<8, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
+            default: batch_tiles<16, HINT, NT, ITERS>(bp, item.tile_begin, item.tile_end, lds, tid); break;
         }
-        __syncthreads();  // tile staged; s_next, written before an earlier barrier, is visible
-        Cur nxt = cur;
-        bool more = true, fetched = false;
-        if (cur.tile + 1 < cur.end) {
-            nxt.tile = cur.tile + 1;
-        } else {
-            idx = __builtin_amdgcn_readfirstlane(s_next);
-            if (idx < last) {
-                const BatchItem item = items[idx];
-                nxt.start(passes[item.pass], item, tid);
-                fetched = true;
-            } else {
-                more = false;
-            }
-        }
-        typename Cur::Parts pn = pc;
-        if (more) {
-            pn = nxt.parts();
-            nxt.template load<HINT>(pn.r, buf, tid);
-        }
-        switch (cur.w) {
-            case 4: cur.template store<4, HINT>(lds, pc, tid); break;
-            case 8: cur.template store<8, HINT>(lds, pc, tid); break;
-            default: cur.template store<16, HINT>(lds, pc, tid); break;
-        }
-        __syncthreads();  // LDS free for the next tile; every thread has read s_next
-        if (!more) break;
-        if (fetched && tid == 0)
-            s_next = first + __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        cur = nxt;
-        pc = pn;
+        __syncthreads();  // s_next written by thread 0 is visible to all
     }
 }
 
