@@ -757,6 +757,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="random26", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="auto", choices=["auto", "tiled", "onepass", "naive"])
+    ap.add_argument("--seed", type=int, default=0, help="seed of the random matrix (random workloads)")
     ap.add_argument("--no-tune", action="store_true", help="time the library defaults, no autotuning")
     ap.add_argument("--retune", action="store_true",
                     help="autotune now instead of taking the options from the tuning file")
@@ -821,7 +822,7 @@ def main():
     from synth import gen
 
     n, w, kind, desc = WORKLOADS[args.workload]
-    rows, c = matrix(kind, n)
+    rows, c = matrix(kind, n, args.seed)
     method = {"auto": B.METHOD_AUTO, "tiled": B.METHOD_TILED, "onepass": B.METHOD_ONEPASS,
               "naive": B.METHOD_NAIVE}[args.method]
 
@@ -955,7 +956,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "elem_bytes": w, "method": args.method,
-                   "passes": passes, "seed": 0, "options": tuned, "tuning": tuning,
+                   "passes": passes, "seed": args.seed, "options": tuned, "tuning": tuning,
                    "cache_state": f"flushed: a {FLUSH_BYTES >> 20} MiB copy between two other buffers before "
                                   "every step, outside the timed interval (the copy bound likewise)"},
         "pct_of_device_copy": round(100.0 * value / dev_copy, 2),
