@@ -154,6 +154,9 @@ struct Server {
 
     void plan_loop();
     void dispatch_loop();
+    // Plan r (no lock held), then record the outcome (lock held).
+    int plan_request(Request* r, BatchArray* ba, bool* solo);
+    void planned(Request* r, int st, const BatchArray& ba, bool solo);
     void finish_slot(Slot& s, int64_t t);
     bool try_admit(Request* r);
     void free_request_memory(Request* r, bool keep_out);
@@ -196,6 +199,39 @@ bool Server::try_admit(Request* r) {
     return true;
 }
 
+int Server::plan_request(Request* r, BatchArray* ba, bool* solo) {
+    const size_t bytes = ((size_t)1 << r->desc.n) * (size_t)r->desc.elem_bytes;
+    *solo = solo_bytes > 0 && bytes >= solo_bytes && r->desc.elem_bytes >= 4;
+    return *solo ? plan_single_array(ds, r->desc, opt.method, ba) : plan_batch_array(ds, r->desc, opt.method, 0, ba);
+}
+
+void Server::planned(Request* r, int st, const BatchArray& ba, bool solo) {
+    if (st != BMMC_OK) {
+        r->status = st;
+        r->state = kFailed;
+        r->done_ns = now_ns();
+        rejected++;
+        if (opt.own_outputs == 2) {  // nobody will poll: forget the request
+            table.erase(r->ticket);
+            delete r;
+        }
+        cv_done.notify_all();
+        return;
+    }
+    r->plan = ba.plan;
+    r->solo = solo;
+    r->grid = ba.grid;
+    r->hints = ba.hints;
+    r->order = ba.order;
+    r->state = kPlanned;
+    r->planned_ns = now_ns();
+    // planners finish out of order: keep `ready` in arrival order
+    auto at = ready.end();
+    while (at != ready.begin() && (*(at - 1))->arrival_ns > r->arrival_ns) --at;
+    ready.insert(at, r);
+    cv_work.notify_all();
+}
+
 void Server::plan_loop() {
     hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
@@ -206,35 +242,10 @@ void Server::plan_loop() {
         to_plan.pop_front();
         lk.unlock();
         BatchArray ba;
-        const size_t bytes = ((size_t)1 << r->desc.n) * (size_t)r->desc.elem_bytes;
-        const bool solo = solo_bytes > 0 && bytes >= solo_bytes && r->desc.elem_bytes >= 4;
-        int st = solo ? plan_single_array(ds, r->desc, opt.method, &ba)
-                      : plan_batch_array(ds, r->desc, opt.method, 0, &ba);
+        bool solo = false;
+        const int st = plan_request(r, &ba, &solo);
         lk.lock();
-        if (st != BMMC_OK) {
-            r->status = st;
-            r->state = kFailed;
-            r->done_ns = now_ns();
-            rejected++;
-            if (opt.own_outputs == 2) {  // nobody will poll: forget the request
-                table.erase(r->ticket);
-                delete r;
-            }
-            cv_done.notify_all();
-            continue;
-        }
-        r->plan = ba.plan;
-        r->solo = solo;
-        r->grid = ba.grid;
-        r->hints = ba.hints;
-        r->order = ba.order;
-        r->state = kPlanned;
-        r->planned_ns = now_ns();
-        // planners finish out of order: keep `ready` in arrival order
-        auto at = ready.end();
-        while (at != ready.begin() && (*(at - 1))->arrival_ns > r->arrival_ns) --at;
-        ready.insert(at, r);
-        cv_work.notify_all();
+        planned(r, st, ba, solo);
     }
 }
 
@@ -274,10 +285,25 @@ void Server::dispatch_loop() {
     while (!stop) {
         bool progress = false;
         const int64_t t = now_ns();
-        // arrivals
+        // arrivals: with nothing queued and a stream free, the dispatcher
+        // plans the request itself and launches it in this same pass (two
+        // thread hand-overs fewer); otherwise the planners take it
         while (!future.empty() && future.top()->arrival_ns <= t) {
-            to_plan.push_back(future.top());
+            Request* r = future.top();
             future.pop();
+            bool free_slot = false;
+            for (const Slot& s : slots) free_slot |= !s.busy;
+            if (free_slot && to_plan.empty() && ready.empty() && admitted.empty()) {
+                lk.unlock();
+                BatchArray ba;
+                bool solo = false;
+                const int st = plan_request(r, &ba, &solo);
+                lk.lock();
+                planned(r, st, ba, solo);
+                progress = true;
+                break;  // admit and launch it before looking at later arrivals
+            }
+            to_plan.push_back(r);
             cv_work.notify_all();
         }
         // completions
