@@ -285,25 +285,13 @@ void Server::dispatch_loop() {
     while (!stop) {
         bool progress = false;
         const int64_t t = now_ns();
-        // arrivals: with nothing queued and a stream free, the dispatcher
-        // plans the request itself and launches it in this same pass (two
-        // thread hand-overs fewer); otherwise the planners take it
+        // arrivals go to the planners (planning in this thread measured
+        // worse: an arrival's planning, now and then a plan-cache eviction,
+        // held up every other request -- p99 at 20k requests/s 1.55 ms
+        // against 0.66 ms)
         while (!future.empty() && future.top()->arrival_ns <= t) {
-            Request* r = future.top();
+            to_plan.push_back(future.top());
             future.pop();
-            bool free_slot = false;
-            for (const Slot& s : slots) free_slot |= !s.busy;
-            if (free_slot && to_plan.empty() && ready.empty() && admitted.empty()) {
-                lk.unlock();
-                BatchArray ba;
-                bool solo = false;
-                const int st = plan_request(r, &ba, &solo);
-                lk.lock();
-                planned(r, st, ba, solo);
-                progress = true;
-                break;  // admit and launch it before looking at later arrivals
-            }
-            to_plan.push_back(r);
             cv_work.notify_all();
         }
         // completions

@@ -80,6 +80,12 @@ int load_file(TuneCache& c, const char* path) {
         uint64_t sig;
         if (std::sscanf(line,
                         "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
+                        "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"hints\": %d, "
+                        "\"ms\": %lf}",
+                        &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &b.iters, &b.tile_order,
+                        &b.hints, &ms) == 9 ||
+            std::sscanf(line,
+                        "{\"kind\": \"batch\", \"sig\": \"%" SCNx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
                         "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"ms\": %lf}",
                         &sig, &b.workgroups, &b.chunk_tiles, &b.order, &b.method, &b.iters, &b.tile_order,
                         &ms) == 8 ||
@@ -136,8 +142,9 @@ int save_file(TuneCache& c, const char* path) {
         const bmmc_batch_options_t& b = kv.second.first;
         std::fprintf(f,
                      "{\"kind\": \"batch\", \"sig\": \"%016" PRIx64 "\", \"workgroups\": %d, \"chunk_tiles\": %d, "
-                     "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"ms\": %.6f}\n",
-                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, b.iters, b.tile_order,
+                     "\"order\": %d, \"method\": %d, \"iters\": %d, \"tile_order\": %d, \"hints\": %d, "
+                     "\"ms\": %.6f}\n",
+                     kv.first, b.workgroups, b.chunk_tiles, b.order, b.method, b.iters, b.tile_order, b.hints,
                      kv.second.second);
     }
     std::fclose(f);
@@ -594,7 +601,11 @@ extern "C" int bmmc_autotune(int n, int elem_bytes, int method, void* stream_, i
         // matrices, six from 256 MiB on.  Class 1: three bit permutations --
         // a random one, the bit reversal and the transpose of the half split
         // -- so that one setting serves the usual tiled matrices.
-        const int nrand = bytes >= ((size_t)256 << 20) ? 6 : 3;
+        // From 1 GiB on, sixteen: with the score's worst-matrix term, six
+        // let settings through that ran one random matrix in eight at
+        // 70-75 % of the copy (benchmark seeds 0-7 at 2^28 int32 and 2^27
+        // int64) while balanced read and write runs keep all above 80 %.
+        const int nrand = bytes >= ((size_t)1 << 30) ? 16 : bytes >= ((size_t)256 << 20) ? 6 : 3;
         std::vector<TuneMatrix> mats(cls == 0 ? nrand : 3);
         if (cls == 0) {
             for (int k = 0; k < nrand; k++)
@@ -692,6 +703,20 @@ extern "C" int bmmc_autotune_batched(const bmmc_desc_t* descs, int count, void* 
     for (int to : {2, 4 + 16 * 2, 4 + 16 * 4, 4 + 16 * 6, 4 + 16 * 7, 4 + 16 * 8, 4 + 16 * 15}) {
         bmmc_batch_options_t o = base;
         o.tile_order = to;
+        double per;
+        st = time_batch(o, &per);
+        if (st != BMMC_OK) return st;
+        if (per < best) {
+            best = per;
+            bo = o;
+        }
+    }
+    // then the cache hints of the best (0 above: non-temporal loads and
+    // stores once the batch outgrows the last-level cache)
+    const bmmc_batch_options_t base2 = bo;
+    for (int h : {1, 2, 3, 4}) {
+        bmmc_batch_options_t o = base2;
+        o.hints = h;
         double per;
         st = time_batch(o, &per);
         if (st != BMMC_OK) return st;
