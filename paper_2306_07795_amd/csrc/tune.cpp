@@ -461,9 +461,17 @@ void tune_matrices(DeviceState* ds, int n, int elem_bytes, int method, bool with
     auto persistent_grid = [&](const bmmc_options_t& o) {
         return ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
     };
+    // BMMC_TUNE_VERBOSE set: a line on stderr every 32 candidates, so that a
+    // long tuning run (minutes for 1 GiB arrays) shows its progress
+    static const bool verbose = std::getenv("BMMC_TUNE_VERBOSE") != nullptr;
+    size_t ntimed = 0;
     auto run = [&](const bmmc_options_t& o) {
         const double t = time_options(n, elem_bytes, mats, o, in, out, stream, cap, reps, tm, fl);
         if (t > 0) timed.push_back({t, o});  // else: the shape does not fit this size
+        if (verbose && ++ntimed % 32 == 0) {
+            std::fprintf(stderr, "autotune n=%d w=%d method=%d: %zu settings timed\n", n, elem_bytes, method, ntimed);
+            std::fflush(stderr);
+        }
     };
     {
         bmmc_options_t o;

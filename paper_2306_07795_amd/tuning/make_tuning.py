@@ -10,6 +10,10 @@ int32 elements) and merges that entry into the file PATH.
 
     BMMC_TUNE_CACHE= python paper_2306_07795_amd/tuning/make_tuning.py --out PATH
     python paper_2306_07795_amd/tuning/make_tuning.py --batched --out PATH
+
+With BMMC_TUNE_CACHE=PATH the library also writes PATH after every size it
+tunes; with BMMC_TUNE_VERBOSE=1 it reports every 32 timed settings on stderr
+(a 1 GiB size takes minutes).
 """
 import argparse
 import os
