@@ -136,6 +136,15 @@ struct Server {
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    // Bumped with every cv_work notification (new arrivals, planned
+    // requests, freed memory, stop): threads that spin instead of sleeping
+    // watch it without taking the lock.
+    std::atomic<uint64_t> work_epoch{0};
+    std::atomic<bool> stopping{false};
+    void notify_work() {
+        work_epoch.fetch_add(1, std::memory_order_release);
+        cv_work.notify_all();
+    }
     std::priority_queue<Request*, std::vector<Request*>, ArrivalLater> future;  // not arrived yet
     std::deque<Request*> to_plan, ready, admitted;
     std::unordered_map<int64_t, Request*> table;
@@ -229,13 +238,27 @@ void Server::planned(Request* r, int st, const BatchArray& ba, bool solo) {
     auto at = ready.end();
     while (at != ready.begin() && (*(at - 1))->arrival_ns > r->arrival_ns) --at;
     ready.insert(at, r);
-    cv_work.notify_all();
+    notify_work();
 }
+
+// Threads that would sleep first spin this long on work_epoch: waking a
+// sleeping thread costs tens of microseconds, about the time the whole path
+// of a small request takes.
+constexpr int64_t kSpinNs = 200000;
 
 void Server::plan_loop() {
     hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
+        if (!stop && to_plan.empty()) {
+            const uint64_t seen = work_epoch.load(std::memory_order_acquire);
+            lk.unlock();
+            const int64_t until = now_ns() + kSpinNs;
+            while (work_epoch.load(std::memory_order_acquire) == seen && !stopping.load(std::memory_order_relaxed) &&
+                   now_ns() < until)
+                __builtin_ia32_pause();
+            lk.lock();
+        }
         cv_work.wait(lk, [&] { return stop || !to_plan.empty(); });
         if (stop) return;
         Request* r = to_plan.front();
@@ -292,7 +315,7 @@ void Server::dispatch_loop() {
         while (!future.empty() && future.top()->arrival_ns <= t) {
             to_plan.push_back(future.top());
             future.pop();
-            cv_work.notify_all();
+            notify_work();
         }
         // completions
         for (Slot& s : slots) {
@@ -382,9 +405,31 @@ void Server::dispatch_loop() {
             }
         }
         if (!progress) {
-            // Sleep until new work arrives or briefly, to poll the streams:
-            // every 5 us (at 20k requests/s, 20 us between polls put about
-            // 10 us on the median latency, measured).
+            // While a stream is busy or an arrival is near, spin: until new
+            // work is queued, the next arrival is due or a busy stream
+            // completes (the streams' events are this thread's own).
+            bool busy_now = false;
+            for (Slot& s : slots) busy_now |= s.busy;
+            const int64_t next_arrival = future.empty() ? INT64_MAX : future.top()->arrival_ns;
+            const int64_t t0 = now_ns();
+            if (busy_now || next_arrival - t0 < kSpinNs) {
+                const uint64_t seen = work_epoch.load(std::memory_order_acquire);
+                lk.unlock();
+                const int64_t until = std::min(t0 + kSpinNs, next_arrival);
+                for (;;) {
+                    if (work_epoch.load(std::memory_order_acquire) != seen || stopping.load(std::memory_order_relaxed))
+                        break;
+                    if (now_ns() >= until) break;
+                    bool done = false;
+                    for (Slot& s : slots) done |= s.busy && hipEventQuery(s.done) == hipSuccess;
+                    if (done) break;
+                    __builtin_ia32_pause();
+                }
+                lk.lock();
+                continue;
+            }
+            // Otherwise sleep until new work arrives or briefly, to poll the
+            // streams every 5 us.
             int64_t wait_ns = 5000;
             if (!future.empty()) wait_ns = std::min<int64_t>(wait_ns, std::max<int64_t>(0, future.top()->arrival_ns - now_ns()));
             bool any_busy = false;
@@ -653,7 +698,7 @@ extern "C" int bmmc_server_submit(void* handle, const bmmc_desc_t* desc, int64_t
     s->submitted++;
     if (s->first_arrival < 0 || r->arrival_ns < s->first_arrival) s->first_arrival = r->arrival_ns;
     s->future.push(r);
-    s->cv_work.notify_all();
+    s->notify_work();
     *ticket_out = r->ticket;
     return BMMC_OK;
 }
@@ -694,7 +739,7 @@ extern "C" int bmmc_server_release(void* handle, int64_t ticket) {
     r->footprint = 0;
     s->table.erase(it);
     delete r;
-    s->cv_work.notify_all();
+    s->notify_work();
     return BMMC_OK;
 }
 
@@ -753,7 +798,8 @@ extern "C" int bmmc_server_destroy(void* handle) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
-        s->cv_work.notify_all();
+        s->stopping.store(true);
+        s->notify_work();
     }
     for (auto& t : s->planners) t.join();
     if (s->dispatcher.joinable()) s->dispatcher.join();
