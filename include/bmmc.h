@@ -493,11 +493,14 @@ typedef struct {
 /* A continuous-batching server on the current device.  It allocates one
    device arena (the largest power of two <= budget_bytes) for outputs and
    scratch, `streams` HIP streams at default priority, four planner threads
-   and one dispatcher thread.
+   and one dispatcher thread (they spin for up to 200 us before sleeping, so
+   a busy server keeps five host cores busy).
    Requests are admitted in arrival order while input + output + scratch of
-   all admitted, unfinished requests fits budget_bytes; every admitted request
-   joins the next launch on a free stream (up to direct_max requests as their
-   own tiled launches, more as one batched persistent launch).
+   all admitted, unfinished requests fits budget_bytes; admitted requests join
+   the next launch on a free stream (up to direct_max requests as their own
+   tiled launches, more as one batched persistent launch; with several
+   streams free, a request planned as its own launch (solo_log2) goes
+   alone and the requests behind it go to the next free stream).
    Errors: _ARG, _NOMEM. */
 int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out);
 

@@ -331,12 +331,24 @@ void Server::dispatch_loop() {
             ready.pop_front();
             progress = true;
         }
-        // launch everything admitted on a free stream
+        // launch what is admitted on the free streams: everything on one
+        // stream, unless another stream is free too -- then a request planned
+        // as its own launch (a large one) goes alone and the requests behind
+        // it to the next free stream, so that small requests do not wait
+        // behind a large one while a stream idles
         if (!admitted.empty()) {
-            for (Slot& s : slots) {
+            for (size_t si = 0; si < slots.size(); si++) {
+                Slot& s = slots[si];
                 if (s.busy) continue;
                 size_t take = admitted.size();
                 if (opt.max_batch > 0) take = std::min(take, (size_t)opt.max_batch);
+                bool other_free = false;
+                for (size_t sj = si + 1; sj < slots.size(); sj++) other_free |= !slots[sj].busy;
+                if (other_free) {
+                    size_t k = 0;
+                    while (k < take && !admitted[k]->solo) k++;
+                    take = k == 0 ? 1 : k;
+                }
                 std::vector<BatchArray> arrays(take);
                 for (size_t i = 0; i < take; i++) {
                     Request* r = admitted[i];
@@ -401,7 +413,7 @@ void Server::dispatch_loop() {
                     batch_reqs += (double)take;
                 }
                 progress = true;
-                break;
+                if (admitted.empty()) break;
             }
         }
         if (!progress) {
