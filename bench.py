@@ -15,8 +15,9 @@ time.  Beside it: the best same-session device copy and the HBM peak as
 fractions, the roofline of the dominant kernel, the paper's two-pass scheme,
 the naive lower bound, the batched form (1024 arrays, one graph launch,
 against 1024 separate calls; p50/p99 of the batch latency), the served form
-(Poisson arrivals, p50/p99 request latency) and the CPU oracle's rate on this
-host.
+(Poisson arrivals at 20k requests/s and, past the server's capacity, at 60k;
+p50/p99 request latency beside the same requests as per-request launches)
+and the CPU oracle's rate on this host.
 """
 from __future__ import annotations
 
@@ -978,6 +979,11 @@ def main():
         line["served"] = bench_served(args.served_rate, args.served_seconds)
         torch.cuda.empty_cache()
         progress("served done")
+        # past the capacity: the same mix at 60k requests/s for 5 s, where
+        # continuous batching carries more than per-request launches
+        line["served_overload"] = bench_served(3.0 * args.served_rate, args.served_seconds / 2, baselines=(4,))
+        torch.cuda.empty_cache()
+        progress("served past capacity done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a, n, rows, c)
     if args.extras_out:
