@@ -438,22 +438,26 @@ def test_tune_cache_classes_round_trip(tmp_path):
 
 
 def test_tune_cache_batch_lines_with_and_without_tile_order(tmp_path):
-    """Batch entries load with a tile order and in the older form without
-    one (tile order 0), and are saved with it."""
+    """Batch entries load with cache hints and a tile order, in the older
+    form without hints (hints 0), and in the oldest without a tile order
+    (tile order 0); they are saved with both."""
     path = tmp_path / "batch.jsonl"
     lines = [
         '{"kind": "batch", "sig": "00000000000000a1", "workgroups": 512, "chunk_tiles": 2, "order": 0, '
         '"method": 0, "iters": 8, "tile_order": 116, "ms": 0.5}',
         '{"kind": "batch", "sig": "00000000000000a2", "workgroups": 1024, "chunk_tiles": 4, "order": 1, '
         '"method": 1, "iters": 4, "ms": 0.75}',
+        '{"kind": "batch", "sig": "00000000000000a3", "workgroups": 256, "chunk_tiles": 1, "order": 0, '
+        '"method": 0, "iters": 32, "tile_order": 2, "hints": 1, "ms": 0.25}',
     ]
     path.write_text("\n".join(lines) + "\n")
-    assert B.bmmc_tune_load(str(path)) == 2
+    assert B.bmmc_tune_load(str(path)) == 3
     out = tmp_path / "again.jsonl"
     B.bmmc_tune_save(str(out))
     saved = {l.split('"sig": "')[1][:16]: l for l in out.read_text().splitlines() if '"kind": "batch"' in l}
-    assert '"tile_order": 116' in saved["00000000000000a1"]
+    assert '"tile_order": 116, "hints": 0' in saved["00000000000000a1"]
     assert '"tile_order": 0' in saved["00000000000000a2"] and '"chunk_tiles": 4' in saved["00000000000000a2"]
+    assert '"tile_order": 2, "hints": 1' in saved["00000000000000a3"] and '"iters": 32' in saved["00000000000000a3"]
 
 
 def test_batch_options_validated():
@@ -465,6 +469,22 @@ def test_batch_options_validated():
         B.bmmc_permute_batched([item], None, {"tile_order": 256})
     with pytest.raises(B.BmmcError, match="iters"):
         B.bmmc_permute_batched([item], None, {"iters": 2})
+
+
+def test_noalloc_batch_options_validated():
+    """The allocation-free batched call checks its options before any device
+    work: the two-pass method (whose scratch would have to be allocated) and
+    bad knobs are refused, and its fixed table has the stated size."""
+    rows, c = gen.random_bmmc(12, 1)
+    item = (1 << 32, (1 << 32) + (1 << 20), 12, 4, rows, c)
+    assert B.bmmc_noalloc_table_bytes() == 4 << 20
+    with pytest.raises(B.BmmcError, match="TILED"):
+        B.bmmc_permute_batched_noalloc([item], None, {"method": B.METHOD_TILED})
+    with pytest.raises(B.BmmcError, match="iters"):
+        B.bmmc_permute_batched_noalloc([item], None, {"iters": 2})
+    with pytest.raises(B.BmmcError, match="tile_order"):
+        B.bmmc_permute_batched_noalloc([item], None, {"tile_order": 256})
+    B.bmmc_permute_batched_noalloc([], None)  # an empty batch is a no-op
 
 
 @pytest.mark.skipif("BMMC_TUNE_CACHE" in os.environ, reason="another tuning file is named")
