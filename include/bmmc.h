@@ -110,7 +110,14 @@ typedef struct {
        XOR-combined iteration bits instead of the lowest free index bits.
        Adding 16*k (k = 1..15) makes the k lowest tile-index bits step the
        output by one write run each (k = 15: every tile-index bit that can),
-       so that tiles running side by side write neighbouring runs. */
+       so that tiles running side by side write neighbouring runs.
+       Adding 256 (with the plain order, 4): where no vector of the tile
+       moves the output's 4 KiB-block index bits (the three bits above a
+       4 KiB block; bit permutations such as the bit reversal and the
+       transposes allow it, random matrices do not), tile t writes only the
+       blocks of index t mod 8 (XOR a constant from c), so that each of the
+       eight XCDs, to which work-groups are dealt in turn, writes one eighth
+       of the blocks; otherwise as without it. */
     int tile_order;
     int reserved[2];
 } bmmc_options_t;
@@ -154,7 +161,7 @@ typedef struct {
     int iters;          /* tile size in 256s of 16-byte vectors: 4 (default: 256 threads x 4
                            vectors, 16 KiB), 8 (256 x 8, 32 KiB), 16 (512 x 8, 64 KiB) or
                            32 (1024 x 8, 128 KiB) */
-    int tile_order;     /* as bmmc_options_t.tile_order, bits 1, 2 and 16*k (0: plain order) */
+    int tile_order;     /* as bmmc_options_t.tile_order, bits 1, 2, 16*k and 256 (0: plain order) */
 } bmmc_batch_options_t;
 
 /* Per-kernel timing gathered between bmmc_profile_begin and _end. */
@@ -174,6 +181,8 @@ typedef struct {
     int64_t lds_instr;                    /* wave-level LDS accesses */
     int64_t lds_conflicts32, lds_conflicts64; /* extra cycles beyond 1 per group */
     int64_t lds_slot_errors;              /* slots not written exactly once / read exactly once */
+    int64_t dealt_write_tiles;            /* tiles writing only 4 KiB blocks of index (tile XOR k) mod 8,
+                                             k that of the pass's tile 0 */
 } bmmc_emu_stats_t;
 
 /* ------------------------------------------------------------ utilities */

@@ -66,7 +66,8 @@ class KernelStat(_c.Structure):
 class EmuStats(_c.Structure):
     _fields_ = [(f, _i64) for f in (
         "tiles", "read_instr", "write_instr", "read_lines", "write_lines", "read_lines_min",
-        "write_lines_min", "lds_instr", "lds_conflicts32", "lds_conflicts64", "lds_slot_errors")]
+        "write_lines_min", "lds_instr", "lds_conflicts32", "lds_conflicts64", "lds_slot_errors",
+        "dealt_write_tiles")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

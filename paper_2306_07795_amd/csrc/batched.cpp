@@ -519,7 +519,7 @@ extern "C" int bmmc_permute_batched_ex(const bmmc_desc_t* descs, int count, cons
     else default_batch_options(descs, count, &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
         return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
-    if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
+    if (o.tile_order < 0 || o.tile_order > 511) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 511]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     hipStream_t stream = (hipStream_t)stream_;
@@ -582,7 +582,7 @@ extern "C" int bmmc_batch_create(const bmmc_desc_t* descs, int count, const bmmc
     else default_batch_options(descs, count, &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
         return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
-    if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
+    if (o.tile_order < 0 || o.tile_order > 511) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 511]");
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     const uint32_t chunk = o.chunk_tiles > 0 ? (uint32_t)o.chunk_tiles : 4u;

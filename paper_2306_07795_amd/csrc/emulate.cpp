@@ -79,8 +79,10 @@ void emulate_pass(const PassTables& P, const KernelShape& ks, int w, const uint8
         gt[tid] = lin(P.G, LV, LT, tid);
     }
     std::vector<int64_t> lane_bytes(64), lane_slot(64);
+    uint32_t class0 = 0;  // 4 KiB-block class (block index mod 8) written by tile 0
     for (uint32_t tile = 0; tile < ntiles; tile++) {
         st->tiles++;
+        uint32_t classes = 0;  // bit k: the tile writes a block of class k
         uint32_t r = 0, yb = P.c_hi, gx = P.c_lds;
         for (uint32_t j = 0; j < P.ntb; j++)
             if ((tile >> j) & 1u) {
@@ -156,6 +158,8 @@ void emulate_pass(const PassTables& P, const KernelShape& ks, int w, const uint8
                         st->lds_conflicts64 += lds_extra(lane_slot, w, 64);
                     }
                 }
+                for (int l = 0; l < 64; l++)
+                    if (lane_bytes[l] >= 0) classes |= 1u << ((lane_bytes[l] >> 12) & 7);
                 const int64_t lines = lines_of(lane_bytes, &active);
                 if (active) {
                     st->write_instr++;
@@ -164,6 +168,8 @@ void emulate_pass(const PassTables& P, const KernelShape& ks, int w, const uint8
                 }
             }
         }
+        if (tile == 0 && classes) class0 = (uint32_t)__builtin_ctz(classes);
+        if (classes == 1u << ((tile ^ class0) & 7u)) st->dealt_write_tiles++;
         const uint32_t valid_slots = vlim * VEC;
         for (uint32_t s = 0; s < ((uint32_t)1 << D); s++) {
             const bool valid = s < valid_slots;

@@ -56,7 +56,7 @@ extern "C" int bmmc_permute_batched_noalloc(const bmmc_desc_t* descs, int count,
     else default_batch_options(descs, count, &o);
     if (o.iters != 0 && o.iters != 4 && o.iters != 8 && o.iters != 16 && o.iters != 32)
         return set_error(BMMC_ERR_ARG, "iters must be 0, 4, 8, 16 or 32");
-    if (o.tile_order < 0 || o.tile_order > 255) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 255]");
+    if (o.tile_order < 0 || o.tile_order > 511) return set_error(BMMC_ERR_ARG, "tile_order outside [0, 511]");
     if (o.method == BMMC_METHOD_TILED)
         return set_error(BMMC_ERR_ARG, "BMMC_METHOD_TILED needs scratch arrays; the allocation-free call "
                                        "runs one pass per array");

@@ -178,6 +178,11 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
 
     uint64_t X[kMaxBits] = {}, Y[kMaxBits] = {}, G0[kMaxBits] = {};
     int d = 0;
+    // The three index bits above a 4 KiB block of elements.
+    int blk = 12;
+    for (int wb = ks.w; wb > 1; wb >>= 1) blk--;
+    const uint64_t block_bits = 7ull << blk;
+    bool dealt = ((tb_mix >> 8) & 1) && n > D && blk + 3 <= n;
     Basis vb;  // read-coordinate basis, inserted in coordinate order
     if (n <= D) {
         // Whole array in one tile: any matrix, read and write fully contiguous.
@@ -233,14 +238,19 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
         }
         p->dim_v0 = d;
         if (d > D) return BMMC_ERR_RANGE;
+        // Dealt output blocks (see the tile-selecting vectors below) need a
+        // tile none of whose vectors moves the output's block bits.
+        for (int k = 0; k < d && dealt; k++) dealt = (T.apply(X[k]) & block_bits) == 0;
         // Iteration bits: the lowest remaining index bits fill the tile.
         // With iter_mix each is XOR-ed with a random choice of the remaining
         // higher index bits, so one tile's rows spread over the address space.
+        // With dealt output blocks, only bits whose images keep the block.
         uint64_t s = seed ^ 0x17E7ull;
         for (int j = a; j < n && d < D; j++) {
+            if (dealt && (T.apply(1ull << j) & block_bits)) continue;
             if (!vb.contains(1ull << j)) {
                 uint64_t v = 1ull << j;
-                if (iter_mix) {
+                if (iter_mix && !dealt) {
                     s = mix64(s);
                     for (int k = j + 1; k < n; k++)
                         if (((s >> (k & 63)) & 1ull) && !vb.contains(1ull << k)) v ^= 1ull << k;
@@ -367,10 +377,36 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
     // are instead the inputs T^-1 e_j of output bits j = b, b+1, ... reduced
     // modulo the tile, so tiles of neighbouring index write neighbouring runs
     // of the output (k = 15: as many as there are).
+    // With bit 8 of tb_mix (dealt output blocks), when the tile allows it,
+    // the first three tile-selecting vectors are the inputs T^-1 e_j of the
+    // output block bits j (the three above a 4 KiB block) and every other one
+    // is made to keep those bits, so tile t writes only the blocks whose
+    // index is t mod 8 (XOR a constant from c).  Work-groups are dealt to the
+    // eight XCDs in turn, so in the plain tile order each XCD then writes one
+    // eighth of the output's 4 KiB blocks, which beyond the last-level cache
+    // the memory system serves faster than XCDs that write them all.
     const int out_adj = (tb_mix >> 4) & 15;
     uint64_t tbv[kMaxBits];
     for (int i = 0; i < ntb; i++) tbv[i] = 1ull << tbpos[i];
-    if (out_adj) {
+    if (dealt && ntb >= 3) {
+        Basis cb = vb;
+        uint64_t u[3];
+        int nt = 0;
+        for (int i = 0; i < 3; i++) {
+            u[i] = vb.reduce(Ti.col(blk + i));
+            if (!u[i] || !cb.insert(u[i])) return BMMC_ERR_INTERNAL;
+            tbv[nt++] = u[i];
+        }
+        for (int k = 0; k < ntb && nt < ntb; k++) {
+            uint64_t v = 1ull << tbpos[k];
+            const uint64_t sig = (T.apply(v) >> blk) & 7ull;
+            for (int i = 0; i < 3; i++)
+                if ((sig >> i) & 1ull) v ^= u[i];
+            v = vb.reduce(v);
+            if (v && cb.insert(v)) tbv[nt++] = v;
+        }
+        if (nt != ntb) return BMMC_ERR_INTERNAL;
+    } else if (out_adj) {
         Basis cb = vb;
         int nt = 0;
         const int want = out_adj == 15 ? ntb : (out_adj < ntb ? out_adj : ntb);

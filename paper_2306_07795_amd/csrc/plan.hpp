@@ -53,7 +53,9 @@ struct PlanOptions {
     int swizzle = 1;  // 0: plain layout, 1: conflict-avoiding XOR layout
     // bit 0: tile-selecting vectors are XOR combinations of index bits;
     // bits 4-7: how many of them step the output (neighbouring tiles write
-    // neighbouring runs; 15 = all); -1: auto
+    // neighbouring runs; 15 = all); bit 8: the first three step the output's
+    // 4 KiB-block bits and no other tile vector moves them, where the tile
+    // allows it (dealt output blocks); -1: auto
     int tb_mix = -1;
     int iter_mix = 0; // 1: iteration vectors are XOR combinations of index bits
     bool shape_given = false;  // false: the default shape for the width and kind of tile

@@ -269,7 +269,7 @@ bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc
 
 int tile_order_mix(int t) {
     if (!t) return -1;
-    return ((t & 4) ? 0 : ((t >> 1) & 1)) | (((t >> 4) & 15) << 4);
+    return ((t & 4) ? 0 : ((t >> 1) & 1)) | (((t >> 4) & 15) << 4) | (t & 256);
 }
 
 PlanOptions plan_options(const bmmc_options_t* o, int w) {
@@ -479,6 +479,8 @@ int bmmc_plan_ex(const uint64_t* A_rows, uint64_t c, int n, int elem_bytes, cons
     if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
         return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
     if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
+    if (opts && (opts->tile_order < 0 || opts->tile_order > 511))
+        return set_error(BMMC_ERR_ARG, "tile_order outside [0, 511]");
     const bmmc_options_t eff = effective_options(nullptr, n, elem_bytes, opts);
     PlanOptions o = plan_options(&eff, elem_bytes);
     Plan p;
@@ -519,6 +521,8 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     if (n < 0 || n > BMMC_MAX_BITS) return set_error(BMMC_ERR_RANGE, "n = %d outside [0, %d]", n, BMMC_MAX_BITS);
     if (!(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4 || elem_bytes == 8 || elem_bytes == 16))
         return set_error(BMMC_ERR_ARG, "elem_bytes = %d not in {1,2,4,8,16}", elem_bytes);
+    if (opts && (opts->tile_order < 0 || opts->tile_order > 511))
+        return set_error(BMMC_ERR_ARG, "tile_order outside [0, 511]");
     const size_t bytes = ((size_t)1 << n) * (size_t)elem_bytes;
     int st = validate_buffers(in, out, bytes);
     if (st != BMMC_OK) return st;

@@ -793,6 +793,24 @@ extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint
         o.tile_order = 2;  // XOR-mixed tile selection
         cands.push_back(o);
     }
+    if (bytes >= kFlushFrom) {
+        // dealt output blocks (where the matrix allows them; else the plain
+        // order), on the base shape and on a 2^12-element tile
+        bmmc_options_t o = base;
+        o.tile_order = 256 + 4;
+        cands.push_back(o);
+        if ((elem_bytes == 4 || elem_bytes == 8) && base.method != BMMC_METHOD_TILED &&
+            tiled_kernel_available(elem_bytes, 512, elem_bytes == 4 ? 2 : 4, 0)) {
+            const int D = 12;
+            o.threads = 512;
+            o.iters = elem_bytes == 4 ? 2 : 4;
+            o.run_in = D / 2 - 1;
+            o.run_out = D - o.run_in;
+            o.t = o.run_in;
+            if (base.grid > 0) o.grid = ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
+            cands.push_back(o);
+        }
+    }
     if ((elem_bytes == 4 || elem_bytes == 8) && base.method != BMMC_METHOD_TILED) {
         for (const auto& sh : kAltShapes) {
             const int b = sh[3] - (elem_bytes == 8 ? 1 : 0);

@@ -146,8 +146,34 @@ def sampled_check(n, rows, c, w, got, a, count=1 << 16, seed=0):
     assert np.array_equal(got[ys], a[xs.astype(np.int64)])
 
 
+DEALT_KINDS = {
+    "reverse": lambda n, w: (gen.identity_rows(n), (1 << n) - 1),
+    "swap7": lambda n, w: (gen.block_swap_rows(n, 7), 0),
+    "bitrev": lambda n, w: (gen.bit_reversal_rows(n), 0),
+    "swap_half": lambda n, w: (gen.block_swap_rows(n, n // 2), 0),
+    "bpc": lambda n, w: gen.random_bpc(n, n + w),
+    "random": lambda n, w: gen.random_bmmc(n, n + w),
+}
+
+
+@pytest.mark.parametrize("small_tile", [False, True])
+@pytest.mark.parametrize("w", [4, 8])
+@pytest.mark.parametrize("kind", sorted(DEALT_KINDS))
+def test_dealt_output_blocks(kind, w, small_tile):
+    """Tile order + 256 (each tile writes 4 KiB blocks of one class where the
+    matrix allows it, the plain choice elsewhere), on the library's shape and
+    on the 2^12-element tile the per-matrix tuner offers with it: in full."""
+    n = 22 if w == 4 else 21
+    rows, c = DEALT_KINDS[kind](n, w)
+    opts = {"tile_order": 256 + 4}
+    if small_tile:
+        opts.update(threads=512, iters=2 if w == 4 else 4, run_in=5, run_out=7)
+    check(n, rows, c, w, fn="ex", opts=opts)
+
+
 @pytest.mark.parametrize("case", ["random28_i32", "random27_i64", "bitrev28_i32", "swap28_i32",
-                                  "swap27_i64", "random28_i32_tiled", "random27_i64_tiled"])
+                                  "swap27_i64", "random28_i32_tiled", "random27_i64_tiled",
+                                  "reverse28_i32_dealt", "swap7_27_i64_dealt"])
 def test_full_size_sweep_sampled(case):
     """The 1 GiB sweep arrays in the benchmark's launch configuration (and in
     the paper's two-pass scheme), checked on 65536 sampled outputs computed
@@ -157,11 +183,21 @@ def test_full_size_sweep_sampled(case):
         rows, c = gen.random_bmmc(n, 1)
     elif case.startswith("bitrev"):
         rows, c = gen.bit_reversal_rows(n), 0
+    elif case.startswith("reverse"):
+        rows, c = gen.identity_rows(n), (1 << n) - 1
+    elif case.startswith("swap7"):
+        rows, c = gen.block_swap_rows(n, 7), 0
     else:
         rows, c = gen.block_swap_rows(n, n // 2), 0
     a = gen.data(n, w, 1)
-    got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_TILED}) if case.endswith("tiled") \
-        else run(n, rows, c, w, a)
+    if case.endswith("tiled"):
+        got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_TILED})
+    elif case.endswith("dealt"):
+        # the setting the per-matrix tuner picks for these (dealt output blocks, 2^12 tile)
+        got = run(n, rows, c, w, a, fn="ex", opts={"tile_order": 256 + 4, "threads": 512, "iters": 2 if w == 4 else 4,
+                                                   "run_in": 5, "run_out": 7})
+    else:
+        got = run(n, rows, c, w, a)
     sampled_check(n, rows, c, w, got, a)
 
 

@@ -325,14 +325,15 @@ def test_emulation_shapes(opts):
         assert st["lds_conflicts64"] == 0
 
 
-@pytest.mark.parametrize("order", [4 + 16, 1 + 16 * 6, 2 + 16 * 3, 4 + 16 * 15])
+@pytest.mark.parametrize("order", [4 + 16, 1 + 16 * 6, 2 + 16 * 3, 4 + 16 * 15, 256 + 4, 256 + 4 + 16 * 7])
 @pytest.mark.parametrize("method", [B.METHOD_AUTO, B.METHOD_TILED])
 @pytest.mark.parametrize("name,mk", [c for c in CASES if c[0] in ("random", "bitrev", "swap", "bpc")],
                          ids=["random", "bitrev", "swap", "bpc"])
 @pytest.mark.parametrize("w", [4, 8])
 def test_emulation_output_ordered_tiles(name, mk, w, method, order):
-    """Tiles selected so that neighbouring tiles write neighbouring runs: the
-    same permutation, every tile still reading and writing whole lines."""
+    """Tiles selected so that neighbouring tiles write neighbouring runs (or,
+    with 256 added, each tile writes 4 KiB blocks of one class): the same
+    permutation, every tile still reading and writing whole lines."""
     n = 17
     rows, c = mk(n, 3 * n + w)
     st = emulate_check(n, rows, c, w, {"method": method, "tile_order": order})
@@ -340,7 +341,7 @@ def test_emulation_output_ordered_tiles(name, mk, w, method, order):
     assert st["write_lines"] == st["write_lines_min"]
 
 
-@pytest.mark.parametrize("order", [4 + 16 * 3, 4 + 16 * 15, 2 + 16 * 15])
+@pytest.mark.parametrize("order", [4 + 16 * 3, 4 + 16 * 15, 2 + 16 * 15, 256 + 4])
 @pytest.mark.parametrize("n", [9, 12, 13, 14, 15])
 def test_output_ordered_tiles_with_few_tile_bits(n, order):
     """k beyond the number of tile-selecting bits (the whole array in one
@@ -348,6 +349,32 @@ def test_output_ordered_tiles_with_few_tile_bits(n, order):
     for rows, c in (gen.random_bmmc(n, 5 * n), (gen.bit_reversal_rows(n), 1)):
         st = emulate_check(n, rows, c, 4, {"tile_order": order})
         assert st["read_lines"] == st["read_lines_min"] and st["write_lines"] == st["write_lines_min"]
+
+
+@pytest.mark.parametrize("w", [4, 8])
+def test_dealt_output_blocks(w):
+    """tile_order + 256: where no tile vector moves the output's 4 KiB-block
+    bits (bit reversal, a transpose whose read runs land above those bits,
+    the identity with any c), every tile writes blocks of one class, the
+    class of tile t being t XOR k mod 8; where the matrix does not allow it
+    (a random matrix, a transpose whose read runs land on those bits) the
+    plan falls back to the plain choice.  Either way the same permutation."""
+    n = 20
+    cases = {"bitrev": (gen.bit_reversal_rows(n), 0), "swap7": (gen.block_swap_rows(n, 7), 0),
+             "identity": (gen.identity_rows(n), 0x5A5A5), "swap_half": (gen.block_swap_rows(n, n // 2), 0),
+             "random": gen.random_bmmc(n, 11)}
+    for name, (rows, c) in cases.items():
+        opts = {"threads": 256, "iters": 4}
+        plain = emulate_check(n, rows, c, w, dict(opts, tile_order=4))
+        dealt = emulate_check(n, rows, c, w, dict(opts, tile_order=256 + 4))
+        assert dealt["write_lines"] == dealt["write_lines_min"]
+        if name in ("bitrev", "swap7", "identity"):
+            assert dealt["dealt_write_tiles"] == dealt["tiles"], name
+            if name != "identity":
+                assert plain["dealt_write_tiles"] < plain["tiles"], name
+        else:
+            # the read runs' images cover the block bits: the plain choice
+            assert dealt["dealt_write_tiles"] == plain["dealt_write_tiles"], name
 
 
 @pytest.mark.parametrize("n,w,a,d", [
@@ -466,7 +493,7 @@ def test_batch_options_validated():
     rows, c = gen.random_bmmc(12, 1)
     item = (1 << 32, (1 << 32) + (1 << 20), 12, 4, rows, c)
     with pytest.raises(B.BmmcError, match="tile_order"):
-        B.bmmc_permute_batched([item], None, {"tile_order": 256})
+        B.bmmc_permute_batched([item], None, {"tile_order": 512})
     with pytest.raises(B.BmmcError, match="iters"):
         B.bmmc_permute_batched([item], None, {"iters": 2})
 
@@ -483,7 +510,7 @@ def test_noalloc_batch_options_validated():
     with pytest.raises(B.BmmcError, match="iters"):
         B.bmmc_permute_batched_noalloc([item], None, {"iters": 2})
     with pytest.raises(B.BmmcError, match="tile_order"):
-        B.bmmc_permute_batched_noalloc([item], None, {"tile_order": 256})
+        B.bmmc_permute_batched_noalloc([item], None, {"tile_order": 512})
     B.bmmc_permute_batched_noalloc([], None)  # an empty batch is a no-op
 
 
