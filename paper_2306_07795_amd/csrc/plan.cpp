@@ -383,8 +383,10 @@ int build_pass(const BitMat& T, uint64_t c, int a, int b, const KernelShape& ks,
     // is made to keep those bits, so tile t writes only the blocks whose
     // index is t mod 8 (XOR a constant from c).  Work-groups are dealt to the
     // eight XCDs in turn, so in the plain tile order each XCD then writes one
-    // eighth of the output's 4 KiB blocks, which beyond the last-level cache
-    // the memory system serves faster than XCDs that write them all.
+    // eighth of the output's 4 KiB blocks.  Beyond the last-level cache that
+    // is faster for some matrices and slower for others (whose reads then
+    // follow the XCDs through coarse address bits), so it is an option that
+    // the per-matrix tuner tries, not a default.
     const int out_adj = (tb_mix >> 4) & 15;
     uint64_t tbv[kMaxBits];
     for (int i = 0; i < ntb; i++) tbv[i] = 1ull << tbpos[i];
