@@ -812,6 +812,23 @@ extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint
         }
     }
     if ((elem_bytes == 4 || elem_bytes == 8) && base.method != BMMC_METHOD_TILED) {
+        // read runs longer than write runs, each XCD on its own range of
+        // tiles whose neighbours write neighbouring runs (the bit reversal's
+        // best beyond the last-level cache)
+        static const int kReadHeavy[][4] = {{1024, 4, 8, 6}, {512, 8, 8, 6}, {256, 16, 8, 6}};
+        for (const auto& sh : kReadHeavy) {
+            const int b = sh[3] - (elem_bytes == 8 ? 1 : 0);
+            if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
+            bmmc_options_t o = base;
+            o.threads = sh[0];
+            o.iters = sh[1];
+            o.run_in = sh[2];
+            o.run_out = b;
+            o.t = b < sh[2] ? b : sh[2];
+            o.tile_order = 1 + 16 * 7;
+            if (base.grid > 0) o.grid = ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
+            cands.push_back(o);
+        }
         for (const auto& sh : kAltShapes) {
             const int b = sh[3] - (elem_bytes == 8 ? 1 : 0);
             if (!tiled_kernel_available(elem_bytes, sh[0], sh[1], 0)) continue;
