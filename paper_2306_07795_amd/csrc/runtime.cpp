@@ -267,6 +267,16 @@ bmmc_options_t effective_options(const DeviceState* ds, int n, int w, const bmmc
     return e;
 }
 
+bool keeps_block_bits(const uint64_t* rows, int n, int w) {
+    int blk = 12;
+    for (int wb = w; wb > 1; wb >>= 1) blk--;
+    if (blk < 0 || blk + 3 > n || !rows) return false;
+    for (int j = blk; j < blk + 3; j++)
+        for (int i = 0; i < n; i++)
+            if (((rows[i] >> j) & 1ull) != (i == j ? 1ull : 0ull)) return false;
+    return true;
+}
+
 int tile_order_mix(int t) {
     if (!t) return -1;
     return ((t & 4) ? 0 : ((t >> 1) & 1)) | (((t >> 4) & 15) << 4) | (t & 256);
@@ -529,10 +539,15 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
     DeviceState* ds = device_state(&st);
     if (!ds) return st;
     bmmc_options_t tuned;
-    if (!opts && (matrix_options(n, elem_bytes, A_rows, &tuned) ||
-                  tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned)))
-        opts = &tuned;
-    const bmmc_options_t eff = effective_options(ds, n, elem_bytes, opts);
+    bool by_class = false;  // options of the matrix's class or the defaults, not the caller's or the matrix's own
+    if (!opts) {
+        by_class = !matrix_options(n, elem_bytes, A_rows, &tuned);
+        if (!by_class || tuned_options(n, elem_bytes, BMMC_METHOD_AUTO, matrix_class(A_rows, n), &tuned))
+            opts = &tuned;
+    }
+    bmmc_options_t eff = effective_options(ds, n, elem_bytes, opts);
+    if (by_class && bytes > kDealtFrom && keeps_block_bits(A_rows, n, elem_bytes))
+        eff.tile_order = 256 + 4;  // dealt output blocks, plain order
     opts = &eff;
     PlanOptions po = plan_options(opts, elem_bytes);
     std::shared_ptr<const Plan> plan;

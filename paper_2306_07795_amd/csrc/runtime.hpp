@@ -111,6 +111,13 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iter
                      int tile_order = 0);
 // PlanOptions::tb_mix of a tile_order option (bits 1, 2 and 16*k; 0: -1, automatic)
 int tile_order_mix(int tile_order);
+// Does A map each of the three index bits above a 4 KiB block of w-byte
+// elements to itself (A e_j = e_j)?  Then dealt output blocks keep each
+// XCD's reads on its own blocks too.
+bool keeps_block_bits(const uint64_t* rows, int n, int w);
+// Arrays above this size (beyond the 256 MB last-level cache) whose matrix
+// keeps its block bits get dealt output blocks by default.
+constexpr size_t kDealtFrom = (size_t)256 << 20;
 // Plan one array as a single-array call without options would run it (the
 // tuned options of its size and matrix class, else the size defaults, for
 // `method`); marks it single, with those launch settings.

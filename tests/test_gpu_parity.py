@@ -173,11 +173,12 @@ def test_dealt_output_blocks(kind, w, small_tile):
 
 @pytest.mark.parametrize("case", ["random28_i32", "random27_i64", "bitrev28_i32", "swap28_i32",
                                   "swap27_i64", "random28_i32_tiled", "random27_i64_tiled",
-                                  "reverse28_i32_dealt", "swap7_27_i64_dealt"])
+                                  "reverse28_i32_dealt", "swap7_27_i64_dealt", "reverse28_i32", "xor27_i64"])
 def test_full_size_sweep_sampled(case):
     """The 1 GiB sweep arrays in the benchmark's launch configuration (and in
-    the paper's two-pass scheme), checked on 65536 sampled outputs computed
-    one by one by the oracle."""
+    the paper's two-pass scheme), and the default call on matrices that keep
+    their 4 KiB-block bits (dealt output blocks by default at this size),
+    checked on 65536 sampled outputs computed one by one by the oracle."""
     n, w = (28, 4) if "i32" in case else (27, 8)
     if case.startswith("random"):
         rows, c = gen.random_bmmc(n, 1)
@@ -185,6 +186,8 @@ def test_full_size_sweep_sampled(case):
         rows, c = gen.bit_reversal_rows(n), 0
     elif case.startswith("reverse"):
         rows, c = gen.identity_rows(n), (1 << n) - 1
+    elif case.startswith("xor"):
+        rows, c = gen.identity_rows(n), gen.random_bmmc(n, 3)[1] | 1
     elif case.startswith("swap7"):
         rows, c = gen.block_swap_rows(n, 7), 0
     else:
