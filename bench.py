@@ -49,6 +49,7 @@ WORKLOADS = {
     "swap28": (28, 4, "swap", "2^14 x 2^14 int32 matrix transpose (bit-block swap)"),
     "swap27x8": (27, 8, "swap", "2^13 x 2^14 int64 matrix transpose (bit-block swap)"),
     "bitrev20": (20, 4, "bitrev", "bit reversal of 2^20 int32 (cache resident)"),
+    "reverse27": (27, 4, "reverse", "reversal x -> x XOR (2^27 - 1) of 2^27 int32 (identity matrix, all-ones c)"),
 }
 
 
@@ -68,6 +69,8 @@ def matrix(kind, n, seed=0):
         return gen.bit_reversal_rows(n), 0
     if kind == "swap":
         return gen.block_swap_rows(n, n // 2), 0
+    if kind == "reverse":
+        return gen.identity_rows(n), (1 << n) - 1
     raise ValueError(kind)
 
 
@@ -338,7 +341,9 @@ def cache_states(x, y, n, rows, c, w, opts, two_pass_opts, stream, flush, reps=2
         return [lambda: B.bmmc_permute_ex(x, m, n, rows, c, w, o, stream),
                 lambda: B.bmmc_permute_ex(m, y, n, rows, c, w, o, stream)]
 
-    variants = {"timed options": opts, "hints 1": dict(opts, hints=1), "hints 3": dict(opts, hints=3)}
+    variants = {"timed options": opts}
+    if opts is not None:  # (None: the library's default call, whose options are its own)
+        variants.update({"hints 1": dict(opts, hints=1), "hints 3": dict(opts, hints=3)})
     out = {}
     for state, before in (("chained", None), ("flushed", flush)):
         cp_us, cp_how = 1e30, None
@@ -766,6 +771,9 @@ def main():
                     help="merge this run's tuning into the JSON-lines file PATH")
     ap.add_argument("--options-from", metavar="BENCH_JSON",
                     help="no autotuning: take the options from the JSON line of an earlier run")
+    ap.add_argument("--default-call", action="store_true",
+                    help="time the call without options (bmmc_permute's own choice) instead of the tuning "
+                         "file's options for the matrix's class")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed permutation and the copy bound (for counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -852,6 +860,11 @@ def main():
             tuned, tuning = B.bmmc_tune_lookup(n, w, rows, method), "autotuned in this run"
     if tuned:
         opts = dict(tuned)
+    if args.default_call:
+        # no options: what bmmc_permute does by itself (its class's tuned
+        # options, and above 256 MiB dealt output blocks for matrices that
+        # keep their 4 KiB-block bits)
+        opts, tuned, tuning = None, None, "none given: the library's default call"
     passes = B.bmmc_plan_ex(rows, c, n, w, opts).nfactors
 
     def step():
