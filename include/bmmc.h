@@ -317,7 +317,8 @@ int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint6
    and the class of A, else with the size-dependent defaults; arrays above
    256 MiB whose A maps each of the three index bits above a 4 KiB block to
    itself (XOR translations such as the reversal, bit permutations of the
-   other bits) take dealt output blocks (tile_order 260) on top of those.  From 64 MiB on
+   other bits) take dealt output blocks (tile_order 260) instead, on
+   16 KiB tiles (512 threads x 2 vectors) for 4- and 8-byte elements.  From 64 MiB on
    these are tuned for a call that finds the caches full of other data (the
    tuner flushes them before every timed call); below, for calls repeated on
    arrays that stay in the caches.  Plans are cached

@@ -116,7 +116,8 @@ int tile_order_mix(int tile_order);
 // XCD's reads on its own blocks too.
 bool keeps_block_bits(const uint64_t* rows, int n, int w);
 // Arrays above this size (beyond the 256 MB last-level cache) whose matrix
-// keeps its block bits get dealt output blocks by default.
+// keeps its block bits get dealt output blocks by default (on 16 KiB tiles
+// for 4- and 8-byte elements).
 constexpr size_t kDealtFrom = (size_t)256 << 20;
 // Plan one array as a single-array call without options would run it (the
 // tuned options of its size and matrix class, else the size defaults, for
