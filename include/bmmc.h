@@ -315,10 +315,11 @@ int bmmc_emulate(const void* in, void* out, int n, const uint64_t* A_rows, uint6
    kernel (the element read at x is written at A.x XOR c).  Runs by
    BMMC_METHOD_AUTO with the options bmmc_autotune stored for (n, elem_bytes)
    and the class of A, else with the size-dependent defaults; arrays above
-   256 MiB whose A maps each of the three index bits above a 4 KiB block to
-   itself (XOR translations such as the reversal, bit permutations of the
-   other bits) take dealt output blocks (tile_order 260) instead, on
-   16 KiB tiles (512 threads x 2 vectors) for 4- and 8-byte elements.  From 64 MiB on
+   256 MiB whose three output index bits above a 4 KiB block depend only on
+   the same three input bits (XOR translations such as the reversal, bit
+   permutations of the other bits) take dealt output blocks (tile_order
+   260) instead, on 16 KiB tiles (512 threads x 2 vectors) for 4- and
+   8-byte elements.  From 64 MiB on
    these are tuned for a call that finds the caches full of other data (the
    tuner flushes them before every timed call); below, for calls repeated on
    arrays that stay in the caches.  Plans are cached

@@ -111,9 +111,10 @@ int plan_batch_array(DeviceState* ds, const bmmc_desc_t& d, int method, int iter
                      int tile_order = 0);
 // PlanOptions::tb_mix of a tile_order option (bits 1, 2 and 16*k; 0: -1, automatic)
 int tile_order_mix(int tile_order);
-// Does A map each of the three index bits above a 4 KiB block of w-byte
-// elements to itself (A e_j = e_j)?  Then dealt output blocks keep each
-// XCD's reads on its own blocks too.
+// Do the three output bits above a 4 KiB block of w-byte elements depend
+// only on the same three input bits (A's rows of those bits inside their
+// columns)?  Then dealt output blocks keep each XCD's reads on its own
+// eighth of the input blocks too.
 bool keeps_block_bits(const uint64_t* rows, int n, int w);
 // Arrays above this size (beyond the 256 MB last-level cache) whose matrix
 // keeps its block bits get dealt output blocks by default (on 16 KiB tiles

@@ -146,7 +146,21 @@ def sampled_check(n, rows, c, w, got, a, count=1 << 16, seed=0):
     assert np.array_equal(got[ys], a[xs.astype(np.int64)])
 
 
+def shear_rows(n, w):
+    """Identity plus three off-diagonal ones: the output bits above a 4 KiB
+    block depend only on the same input bits (mixed among themselves), but
+    one of those input bits also reaches a higher output bit and another a
+    lower one."""
+    blk = 12 - (w.bit_length() - 1)
+    rows = gen.identity_rows(n)
+    rows[20] |= 1 << blk
+    rows[blk + 1] |= 1 << blk
+    rows[5] |= 1 << (blk + 2)
+    return rows
+
+
 DEALT_KINDS = {
+    "shear": lambda n, w: (shear_rows(n, w), 12345),
     "reverse": lambda n, w: (gen.identity_rows(n), (1 << n) - 1),
     "swap7": lambda n, w: (gen.block_swap_rows(n, 7), 0),
     "bitrev": lambda n, w: (gen.bit_reversal_rows(n), 0),
@@ -173,7 +187,8 @@ def test_dealt_output_blocks(kind, w, small_tile):
 
 @pytest.mark.parametrize("case", ["random28_i32", "random27_i64", "bitrev28_i32", "swap28_i32",
                                   "swap27_i64", "random28_i32_tiled", "random27_i64_tiled",
-                                  "reverse28_i32_dealt", "swap7_27_i64_dealt", "reverse28_i32", "xor27_i64"])
+                                  "reverse28_i32_dealt", "swap7_27_i64_dealt", "reverse28_i32", "xor27_i64",
+                                  "shear28_i32", "shear27_i64"])
 def test_full_size_sweep_sampled(case):
     """The 1 GiB sweep arrays in the benchmark's launch configuration (and in
     the paper's two-pass scheme), and the default call on matrices that keep
@@ -188,6 +203,8 @@ def test_full_size_sweep_sampled(case):
         rows, c = gen.identity_rows(n), (1 << n) - 1
     elif case.startswith("xor"):
         rows, c = gen.identity_rows(n), gen.random_bmmc(n, 3)[1] | 1
+    elif case.startswith("shear"):
+        rows, c = shear_rows(n, w), 12345
     elif case.startswith("swap7"):
         rows, c = gen.block_swap_rows(n, 7), 0
     else:
