@@ -795,19 +795,21 @@ extern "C" int bmmc_autotune_matrix(const void* in, void* out, int n, const uint
     }
     if (bytes >= kFlushFrom) {
         // dealt output blocks (where the matrix allows them; else the plain
-        // order), on the base shape and on a 2^12-element tile
+        // order), on the base shape and on a 16 KiB tile (512 threads x 2
+        // vectors, one work-group per tile: the default's setting for
+        // matrices that keep their block bits)
         bmmc_options_t o = base;
         o.tile_order = 256 + 4;
         cands.push_back(o);
         if ((elem_bytes == 4 || elem_bytes == 8) && base.method != BMMC_METHOD_TILED &&
-            tiled_kernel_available(elem_bytes, 512, elem_bytes == 4 ? 2 : 4, 0)) {
-            const int D = 12;
+            tiled_kernel_available(elem_bytes, 512, 2, 1)) {
             o.threads = 512;
-            o.iters = elem_bytes == 4 ? 2 : 4;
-            o.run_in = D / 2 - 1;
-            o.run_out = D - o.run_in;
+            o.iters = 2;
+            o.run_in = elem_bytes == 4 ? 5 : 4;
+            o.run_out = 7;
             o.t = o.run_in;
-            if (base.grid > 0) o.grid = ds->cu_count * tiled_occupancy(elem_bytes, o.threads, o.iters, 0) * 2;
+            o.hints = 1;
+            o.grid = -1;
             cands.push_back(o);
         }
     }

@@ -176,12 +176,12 @@ DEALT_KINDS = {
 def test_dealt_output_blocks(kind, w, small_tile):
     """Tile order + 256 (each tile writes 4 KiB blocks of one class where the
     matrix allows it, the plain choice elsewhere), on the library's shape and
-    on the 2^12-element tile the per-matrix tuner offers with it: in full."""
+    on the 16 KiB tile the per-matrix tuner offers with it: in full."""
     n = 22 if w == 4 else 21
     rows, c = DEALT_KINDS[kind](n, w)
     opts = {"tile_order": 256 + 4}
     if small_tile:
-        opts.update(threads=512, iters=2 if w == 4 else 4, run_in=5, run_out=7)
+        opts.update(threads=512, iters=2, run_in=5 if w == 4 else 4, run_out=7)
     check(n, rows, c, w, fn="ex", opts=opts)
 
 
@@ -213,9 +213,9 @@ def test_full_size_sweep_sampled(case):
     if case.endswith("tiled"):
         got = run(n, rows, c, w, a, fn="ex", opts={"method": B.METHOD_TILED})
     elif case.endswith("dealt"):
-        # the setting the per-matrix tuner picks for these (dealt output blocks, 2^12 tile)
-        got = run(n, rows, c, w, a, fn="ex", opts={"tile_order": 256 + 4, "threads": 512, "iters": 2 if w == 4 else 4,
-                                                   "run_in": 5, "run_out": 7})
+        # dealt output blocks on the 16 KiB tile (the per-matrix tuner's candidate)
+        got = run(n, rows, c, w, a, fn="ex", opts={"tile_order": 256 + 4, "threads": 512, "iters": 2,
+                                                   "run_in": 5 if w == 4 else 4, "run_out": 7})
     else:
         got = run(n, rows, c, w, a)
     sampled_check(n, rows, c, w, got, a)
