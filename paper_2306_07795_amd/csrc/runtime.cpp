@@ -278,6 +278,24 @@ bool keeps_block_bits(const uint64_t* rows, int n, int w) {
     return true;
 }
 
+void dealt_default(bmmc_options_t* e, const uint64_t* rows, int n, int w) {
+    const size_t bytes = ((size_t)1 << n) * (size_t)w;
+    if (bytes <= kDealtFrom || !keeps_block_bits(rows, n, w)) return;
+    e->tile_order = 256 + 4;  // dealt output blocks, plain order
+    if (w == 4 || w == 8) {
+        // 16 KiB tiles (512 threads x 2 vectors), one work-group each,
+        // non-temporal loads and cached stores: the fastest dealt setting
+        // measured for these matrices beyond the last-level cache
+        e->threads = 512;
+        e->iters = 2;
+        e->run_in = w == 4 ? 5 : 4;
+        e->run_out = 7;
+        e->t = e->run_in;
+        e->hints = 1;
+        e->grid = -1;
+    }
+}
+
 int tile_order_mix(int t) {
     if (!t) return -1;
     return ((t & 4) ? 0 : ((t >> 1) & 1)) | (((t >> 4) & 15) << 4) | (t & 256);
@@ -415,10 +433,12 @@ int plan_single_array(DeviceState* ds, const bmmc_desc_t& d, int method, BatchAr
     bmmc_options_t o;
     std::memset(&o, 0, sizeof(o));
     o.method = method;
-    // the options tuned for this matrix, else for its class, else the defaults
-    if (!(method == BMMC_METHOD_AUTO && matrix_options(d.n, d.elem_bytes, d.A_rows, &o)))
-        tuned_options(d.n, d.elem_bytes, method, matrix_class(d.A_rows, d.n), &o);
-    const bmmc_options_t eff = effective_options(ds, d.n, d.elem_bytes, &o);
+    // the options tuned for this matrix, else for its class, else the
+    // defaults (with the default call's dealt output blocks where they apply)
+    const bool own = method == BMMC_METHOD_AUTO && matrix_options(d.n, d.elem_bytes, d.A_rows, &o);
+    if (!own) tuned_options(d.n, d.elem_bytes, method, matrix_class(d.A_rows, d.n), &o);
+    bmmc_options_t eff = effective_options(ds, d.n, d.elem_bytes, &o);
+    if (!own && method == BMMC_METHOD_AUTO) dealt_default(&eff, d.A_rows, d.n, d.elem_bytes);
     const int st = get_plan(ds, d.A_rows, d.c, d.n, d.elem_bytes, plan_options(&eff, d.elem_bytes), &out->plan);
     if (st != BMMC_OK) return st;
     out->in = d.in;
@@ -547,21 +567,7 @@ int bmmc_permute_ex(const void* in, void* out, int n, const uint64_t* A_rows, ui
             opts = &tuned;
     }
     bmmc_options_t eff = effective_options(ds, n, elem_bytes, opts);
-    if (by_class && bytes > kDealtFrom && keeps_block_bits(A_rows, n, elem_bytes)) {
-        eff.tile_order = 256 + 4;  // dealt output blocks, plain order
-        if (elem_bytes == 4 || elem_bytes == 8) {
-            // 16 KiB tiles (512 threads x 2 vectors), one work-group each,
-            // non-temporal loads and cached stores: the fastest dealt setting
-            // measured for these matrices beyond the last-level cache
-            eff.threads = 512;
-            eff.iters = 2;
-            eff.run_in = elem_bytes == 4 ? 5 : 4;
-            eff.run_out = 7;
-            eff.t = eff.run_in;
-            eff.hints = 1;
-            eff.grid = -1;
-        }
-    }
+    if (by_class) dealt_default(&eff, A_rows, n, elem_bytes);
     opts = &eff;
     PlanOptions po = plan_options(opts, elem_bytes);
     std::shared_ptr<const Plan> plan;

@@ -120,6 +120,8 @@ bool keeps_block_bits(const uint64_t* rows, int n, int w);
 // keeps its block bits get dealt output blocks by default (on 16 KiB tiles
 // for 4- and 8-byte elements).
 constexpr size_t kDealtFrom = (size_t)256 << 20;
+// Those defaults applied to effective options *e (nothing for other arrays).
+void dealt_default(bmmc_options_t* e, const uint64_t* rows, int n, int w);
 // Plan one array as a single-array call without options would run it (the
 // tuned options of its size and matrix class, else the size defaults, for
 // `method`); marks it single, with those launch settings.

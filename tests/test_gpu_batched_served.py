@@ -443,3 +443,29 @@ def test_server_batched_launches_only(use_graph):
             B.bmmc_server_release(srv, tk)
     finally:
         B.bmmc_server_destroy(srv)
+
+
+def test_server_large_block_preserving_request():
+    """A 512 MiB request whose matrix keeps its 4 KiB-block bits (the
+    reversal), planned as a single-array call: the server plans it as the
+    default call does (dealt output blocks on 16 KiB tiles); its output is
+    the permutation on 65536 sampled outputs computed by the oracle."""
+    n, w = 26, 8
+    rows, c = gen.identity_rows(n), (1 << n) - 1
+    a = gen.data(n, w, 4)
+    x = G.to_device(a)
+    srv = B.bmmc_server_create(2 << 30, streams=2, own_outputs=True, solo_log2=16)
+    try:
+        tk = B.bmmc_server_submit(srv, x, 0, n, rows, c, w)
+        done, out = B.bmmc_server_poll(srv, tk, wait=True)
+        y = torch.empty(a.nbytes, dtype=torch.uint8, device=G.dev())
+        B.bmmc_copy(out, y, a.nbytes, G.stream())
+        G.sync()
+        got = G.to_host(y, a)
+        B.bmmc_server_release(srv, tk)
+    finally:
+        B.bmmc_server_destroy(srv)
+    xs = np.random.default_rng(5).integers(0, 1 << n, size=1 << 16, dtype=np.uint64)
+    xs[:2] = [0, (1 << n) - 1]
+    ys = O.apply_many(rows, c, n, xs).astype(np.int64)
+    assert np.array_equal(got[ys], a[xs.astype(np.int64)])
