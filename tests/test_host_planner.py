@@ -377,6 +377,20 @@ def test_dealt_output_blocks(w):
             assert dealt["dealt_write_tiles"] == plain["dealt_write_tiles"], name
 
 
+@pytest.mark.parametrize("w", [1, 2, 16])
+def test_dealt_output_blocks_other_widths(w):
+    """Dealt output blocks with 1-, 2- and 16-byte elements (the block bits
+    sit 12 - log2(w) bits up): the reversal is dealt in every tile, and the
+    permutation is exact for it, the bit reversal and a random matrix."""
+    n = 18
+    for name, (rows, c) in {"reverse": (gen.identity_rows(n), (1 << n) - 1),
+                            "bitrev": (gen.bit_reversal_rows(n), 0),
+                            "random": gen.random_bmmc(n, 3)}.items():
+        st = emulate_check(n, rows, c, w, {"tile_order": 256 + 4})
+        if name == "reverse":
+            assert st["dealt_write_tiles"] == st["tiles"]
+
+
 @pytest.mark.parametrize("n,w,a,d", [
     (21, 4, 6, 13),   # 8 MiB: the general tile's own default
     (22, 4, 5, 13),   # 16 MiB: 256 x 8 vectors, 2^5-element reads
