@@ -561,8 +561,18 @@ hipError_t launch_naive(int w, int n, const void* in, void* out, const NaiveArgs
 template <int VPT, int HINT>
 __global__ void __launch_bounds__(256)
 k_copy(const u32x4* __restrict__ in, u32x4* __restrict__ out, uint64_t nvec) {
-    const uint64_t base = (uint64_t)blockIdx.x * (256 * VPT) + threadIdx.x;
+    const uint64_t first = (uint64_t)blockIdx.x * (256 * VPT);
+    const uint64_t base = first + threadIdx.x;
     u32x4 v[VPT];
+    if (first + 256 * VPT <= nvec) {
+        // a whole chunk (every work-group but the last): no per-vector tests,
+        // so the loads go out back to back instead of one at a time
+#pragma unroll
+        for (int k = 0; k < VPT; k++) v[k] = ld16<HINT>((const g_u32x4*)in + base + k * 256);
+#pragma unroll
+        for (int k = 0; k < VPT; k++) st16<HINT>((g_u32x4*)out + base + k * 256, v[k]);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < VPT; k++)
         if (base + k * 256 < nvec) v[k] = ld16<HINT>((const g_u32x4*)in + base + k * 256);
