@@ -501,6 +501,16 @@ def test_tune_cache_batch_lines_with_and_without_tile_order(tmp_path):
     assert '"tile_order": 2, "hints": 1' in saved["00000000000000a3"] and '"iters": 32' in saved["00000000000000a3"]
 
 
+def test_tile_order_range_checked_when_planning():
+    """Tile orders run from 0 to 511 (bit 8: dealt output blocks); planning
+    refuses others with an argument error."""
+    rows, c = gen.random_bmmc(14, 2)
+    assert B.bmmc_plan_ex(rows, c, 14, 4, {"tile_order": 256 + 4}).nfactors == 1
+    for bad in (-1, 512):
+        with pytest.raises(B.BmmcError, match="tile_order"):
+            B.bmmc_plan_ex(rows, c, 14, 4, {"tile_order": bad})
+
+
 def test_batch_options_validated():
     """Options are checked before any device work (addresses are never
     dereferenced: the call fails first)."""
