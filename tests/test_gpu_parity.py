@@ -221,6 +221,16 @@ def test_full_size_sweep_sampled(case):
     sampled_check(n, rows, c, w, got, a)
 
 
+@pytest.mark.parametrize("n,w", [(25, 16), (28, 2)])
+def test_default_call_dealt_other_widths(n, w):
+    """The default call's dealt output blocks for 16- and 2-byte elements
+    (512 MiB, the class options' shape): the reversal, on sampled outputs."""
+    rows, c = gen.identity_rows(n), (1 << n) - 1
+    a = gen.data(n, w, 6)
+    got = run(n, rows, c, w, a)
+    sampled_check(n, rows, c, w, got, a)
+
+
 @pytest.mark.parametrize("kind", ["random", "bitrev"])
 @pytest.mark.parametrize("n,w", [(22, 4), (23, 4), (24, 4), (21, 8), (22, 8), (23, 8), (27, 4), (26, 8)])
 def test_size_dependent_defaults(n, w, kind):
