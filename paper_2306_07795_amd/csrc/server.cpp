@@ -299,6 +299,9 @@ void Server::finish_slot(Slot& s, int64_t t) {
     s.busy = false;
 }
 
+// Queues up to this many admitted requests count as short (see below).
+constexpr size_t kShortQueue = 16;
+
 void Server::dispatch_loop() {
     hipSetDevice(device);
     // Timed waits of this thread end on time: Linux lets a sleeping thread
@@ -331,11 +334,14 @@ void Server::dispatch_loop() {
             ready.pop_front();
             progress = true;
         }
-        // launch what is admitted on the free streams: everything on one
-        // stream, unless another stream is free too -- then a request planned
-        // as its own launch (a large one) goes alone and the requests behind
-        // it to the next free stream, so that small requests do not wait
-        // behind a large one while a stream idles
+        // launch what is admitted on the free streams, in arrival order.
+        // While the queue is short (or another stream is free): the leading
+        // run of requests planned into a shared launch (small ones)
+        // together, or a request planned as its own launch (a large one)
+        // alone, the rest to the next free stream, so that small requests do
+        // not share a launch, and its completion, with a large one.  When the
+        // queue is long (the load exceeds what the streams carry), everything
+        // queued in one launch: batching is then what keeps up.
         if (!admitted.empty()) {
             for (size_t si = 0; si < slots.size(); si++) {
                 Slot& s = slots[si];
@@ -344,7 +350,7 @@ void Server::dispatch_loop() {
                 if (opt.max_batch > 0) take = std::min(take, (size_t)opt.max_batch);
                 bool other_free = false;
                 for (size_t sj = si + 1; sj < slots.size(); sj++) other_free |= !slots[sj].busy;
-                if (other_free) {
+                if (other_free || admitted.size() <= kShortQueue) {
                     size_t k = 0;
                     while (k < take && !admitted[k]->solo) k++;
                     take = k == 0 ? 1 : k;
