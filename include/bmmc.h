@@ -512,10 +512,11 @@ typedef struct {
    Requests are admitted in arrival order while input + output + scratch of
    all admitted, unfinished requests fits budget_bytes; admitted requests join
    the next launch on a free stream (up to direct_max requests as their own
-   tiled launches, more as one batched persistent launch); a request planned
-   as its own launch (solo_log2) always goes alone, and a launch takes only
-   the run of small requests ahead of the next such request, the rest going
-   to the next free stream.
+   tiled launches, more as one batched persistent launch); while another
+   stream is free or at most 16 requests wait, a request planned as its own
+   launch (solo_log2) goes alone and a launch takes only the run of small
+   requests ahead of the next such request, the rest going to the next free
+   stream; a longer queue goes into one launch.
    Errors: _ARG, _NOMEM. */
 int bmmc_server_create(const bmmc_server_options_t* opts, void** handle_out);
 
